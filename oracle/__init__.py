@@ -1,0 +1,294 @@
+"""CPU oracle for the ZMCintegral method (arXiv:1902.07916, Sec. 2.1).
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  The product package never imports this
+module and this module imports nothing from the product package.
+
+The arithmetic lives in ``zmc_oracle.c`` (plain single-threaded FP64 C, built
+with ``-ffp-contract=off`` and no fast-math); this file only marshals arguments
+through ctypes and exposes the runs as numpy arrays.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "zmc_oracle.c")
+BUILD_DIR = os.path.join(HERE, "_build")
+LIB_PATH = os.path.join(BUILD_DIR, "libzmc_oracle.so")
+
+MAX_DIM = 16
+MAX_LEVELS = 16
+MAX_PARAMS = 2 * MAX_DIM + 2
+
+GAUSS, SIN_SUM, GENZ_OSC, GENZ_PPEAK, GENZ_CPEAK, GENZ_GAUSS, CONST, MONOMIAL = range(8)
+OK, EINVAL, ENOMEM, ENONFINITE = 0, -1, -2, -3
+F_TRUNCATED, F_RTOL_MET = 1, 2
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc into ``oracle/_build`` and return the path."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC):
+        tmp = LIB_PATH + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-std=c11", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared",
+               "-Wall", "-Wextra", "-o", tmp, SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+class Problem(C.Structure):
+    _fields_ = [
+        ("integrand", C.c_int32), ("dim", C.c_int32), ("divisions", C.c_int32),
+        ("trials", C.c_int32), ("max_depth", C.c_int32), ("n_params", C.c_int32),
+        ("samples", C.c_int64), ("max_cubes_per_level", C.c_int64),
+        ("sigma_mult", C.c_double), ("rtol", C.c_double), ("seed", C.c_uint64),
+        ("lower", C.c_double * MAX_DIM), ("upper", C.c_double * MAX_DIM),
+        ("params", C.c_double * MAX_PARAMS),
+    ]
+
+
+class Replay(C.Structure):
+    _fields_ = [
+        ("n_levels", C.c_int32),
+        ("n", C.c_int64 * MAX_LEVELS),
+        ("uid", C.POINTER(C.c_uint64) * MAX_LEVELS),
+        ("sel", C.POINTER(C.c_uint8) * MAX_LEVELS),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = LIB_PATH if os.path.exists(LIB_PATH) else build()
+        L = C.CDLL(path)
+        P = C.POINTER(Problem)
+        L.oracle_philox4x32_10.argtypes = [C.POINTER(C.c_uint32), C.POINTER(C.c_uint32), C.POINTER(C.c_uint32)]
+        L.oracle_uniform.argtypes = [C.c_uint32]
+        L.oracle_uniform.restype = C.c_double
+        L.oracle_word.argtypes = [C.c_uint64, C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_int64, C.c_int]
+        L.oracle_word.restype = C.c_uint32
+        L.oracle_cube_lattice.argtypes = [C.c_int, C.c_int, C.c_int, C.c_uint64, C.POINTER(C.c_uint64)]
+        L.oracle_cube_bounds.argtypes = [P, C.c_int, C.c_uint64, C.POINTER(C.c_double),
+                                         C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.oracle_n_params.argtypes = [C.c_int, C.c_int]
+        L.oracle_f.argtypes = [C.c_int, C.POINTER(C.c_double), C.c_int, C.POINTER(C.c_double)]
+        L.oracle_f.restype = C.c_double
+        L.oracle_sample_x.argtypes = [P, C.c_int, C.c_uint64, C.c_int, C.c_int64, C.POINTER(C.c_double)]
+        L.oracle_cube_trial.argtypes = [P, C.c_int, C.c_uint64, C.c_int, C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.oracle_cube.argtypes = [P, C.c_int, C.c_uint64, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.oracle_threshold.argtypes = [C.POINTER(C.c_double), C.c_int64, C.c_double,
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.oracle_threshold.restype = C.c_double
+        L.oracle_children.argtypes = [C.c_uint64, C.c_int, C.POINTER(C.c_uint64)]
+        L.oracle_validate.argtypes = [P]
+        L.oracle_integrate.argtypes = [P, C.POINTER(Replay), C.c_double]
+        L.oracle_integrate.restype = C.c_void_p
+        L.oracle_free.argtypes = [C.c_void_p]
+        for name in ("oracle_run_status", "oracle_run_flags", "oracle_run_levels"):
+            getattr(L, name).argtypes = [C.c_void_p]
+        L.oracle_run_totals.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
+        L.oracle_level_n.argtypes = [C.c_void_p, C.c_int]
+        L.oracle_level_n.restype = C.c_int64
+        for name, t in (("oracle_level_uid", C.c_uint64), ("oracle_level_m", C.c_double),
+                        ("oracle_level_s", C.c_double), ("oracle_level_I", C.c_double),
+                        ("oracle_level_sa", C.c_double), ("oracle_level_sel", C.c_uint8)):
+            f = getattr(L, name)
+            f.argtypes = [C.c_void_p, C.c_int]
+            f.restype = C.POINTER(t)
+        L.oracle_level_stats.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        if L.oracle_sizeof_problem() != C.sizeof(Problem):
+            raise RuntimeError("oracle_problem layout mismatch")
+        _lib = L
+    return _lib
+
+
+def problem(integrand, dim, lower, upper, divisions, samples, trials, max_depth, sigma_mult, seed,
+            params=(), rtol=0.0, max_cubes_per_level=1 << 24) -> Problem:
+    p = Problem()
+    p.integrand, p.dim, p.divisions = int(integrand), int(dim), int(divisions)
+    p.trials, p.max_depth, p.n_params = int(trials), int(max_depth), len(params)
+    p.samples, p.max_cubes_per_level = int(samples), int(max_cubes_per_level)
+    p.sigma_mult, p.rtol, p.seed = float(sigma_mult), float(rtol), int(seed) & ((1 << 64) - 1)
+    nd = max(0, min(int(dim), MAX_DIM))
+    lower = np.broadcast_to(np.asarray(lower, dtype=np.float64), (nd,))
+    upper = np.broadcast_to(np.asarray(upper, dtype=np.float64), (nd,))
+    for i in range(nd):
+        p.lower[i] = float(lower[i])
+        p.upper[i] = float(upper[i])
+    if len(params) > MAX_PARAMS:
+        raise ValueError("too many params")
+    for j, v in enumerate(params):
+        p.params[j] = float(v)
+    return p
+
+
+def philox(ctr, key):
+    c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (C.c_uint32 * 4)()
+    lib().oracle_philox4x32_10(c, k, o)
+    return tuple(o)
+
+
+def uniform(w: int) -> float:
+    return lib().oracle_uniform(int(w) & 0xFFFFFFFF)
+
+
+def word(seed, uid, level, trial, dim, s, i) -> int:
+    return lib().oracle_word(int(seed), int(uid), int(level), int(trial), int(dim), int(s), int(i))
+
+
+def lattice(dim, divisions, level, uid):
+    K = (C.c_uint64 * MAX_DIM)()
+    lib().oracle_cube_lattice(dim, divisions, level, int(uid), K)
+    return np.array(K[:dim], dtype=np.uint64)
+
+
+def bounds(p: Problem, level: int, uid: int):
+    lo = (C.c_double * MAX_DIM)()
+    h = (C.c_double * MAX_DIM)()
+    v = C.c_double()
+    lib().oracle_cube_bounds(C.byref(p), level, int(uid), lo, h, C.byref(v))
+    return np.array(lo[:p.dim]), np.array(h[:p.dim]), v.value
+
+
+def f(integrand, params, x) -> float:
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    prm = (C.c_double * MAX_PARAMS)(*[float(v) for v in params])
+    return lib().oracle_f(int(integrand), prm, len(x), x.ctypes.data_as(C.POINTER(C.c_double)))
+
+
+def sample_x(p: Problem, level, uid, trial, s):
+    x = (C.c_double * MAX_DIM)()
+    lib().oracle_sample_x(C.byref(p), level, int(uid), trial, int(s), x)
+    return np.array(x[:p.dim])
+
+
+def cube_trial(p: Problem, level, uid, trial):
+    I, S1, S2, SA = C.c_double(), C.c_double(), C.c_double(), C.c_double()
+    st = lib().oracle_cube_trial(C.byref(p), level, int(uid), trial, C.byref(I), C.byref(S1),
+                                 C.byref(S2), C.byref(SA))
+    return st, I.value, S1.value, S2.value, SA.value
+
+
+def cube(p: Problem, level, uid):
+    I = (C.c_double * p.trials)()
+    m, s, sa = C.c_double(), C.c_double(), C.c_double()
+    st = lib().oracle_cube(C.byref(p), level, int(uid), I, C.byref(m), C.byref(s), C.byref(sa))
+    return st, np.array(I[:]), m.value, s.value, sa.value
+
+
+def threshold(s, sigma_mult):
+    s = np.ascontiguousarray(s, dtype=np.float64)
+    mu, sd = C.c_double(), C.c_double()
+    thr = lib().oracle_threshold(s.ctypes.data_as(C.POINTER(C.c_double)), len(s), float(sigma_mult),
+                                 C.byref(mu), C.byref(sd))
+    return thr, mu.value, sd.value
+
+
+def children(uid, dim):
+    out = (C.c_uint64 * (1 << dim))()
+    lib().oracle_children(int(uid), dim, out)
+    return np.array(out[:], dtype=np.uint64)
+
+
+def validate(p: Problem) -> int:
+    return lib().oracle_validate(C.byref(p))
+
+
+@dataclass
+class Level:
+    n: int
+    uid: np.ndarray
+    m: np.ndarray
+    s: np.ndarray
+    I: np.ndarray
+    sa: np.ndarray
+    sel: np.ndarray
+    thr: float
+    mu: float
+    sd: float
+    min_margin: float
+    n_sel: int
+    n_in_band: int
+    n_replayed: int
+
+
+@dataclass
+class Run:
+    status: int
+    flags: int
+    integral: float = float("nan")
+    std: float = float("nan")
+    stderr: float = float("nan")
+    sum_abs: float = float("nan")
+    n_samples: int = 0
+    n_cubes: int = 0
+    levels: list = field(default_factory=list)
+
+
+def integrate(p: Problem, replay=None, band_eps: float = 0.0) -> Run:
+    """Run the whole tree search.  ``replay``: list (per level) of (uids, sel)
+    from another run; decisions inside the ``band_eps`` margin are adopted."""
+    L = lib()
+    rp = None
+    keep = []
+    if replay is not None:
+        rp = Replay()
+        rp.n_levels = len(replay)
+        for l, (u, s) in enumerate(replay):
+            u = np.ascontiguousarray(u, dtype=np.uint64)
+            s = np.ascontiguousarray(s, dtype=np.uint8)
+            order = np.argsort(u, kind="stable")
+            u, s = np.ascontiguousarray(u[order]), np.ascontiguousarray(s[order])
+            keep += [u, s]
+            rp.n[l] = len(u)
+            rp.uid[l] = u.ctypes.data_as(C.POINTER(C.c_uint64))
+            rp.sel[l] = s.ctypes.data_as(C.POINTER(C.c_uint8))
+    h = L.oracle_integrate(C.byref(p), C.byref(rp) if rp is not None else None, float(band_eps))
+    if not h:
+        raise MemoryError("oracle_integrate")
+    try:
+        run = Run(status=L.oracle_run_status(h), flags=L.oracle_run_flags(h))
+        tot = (C.c_double * 4)()
+        cnt = (C.c_uint64 * 2)()
+        L.oracle_run_totals(h, tot, cnt)
+        run.integral, run.std, run.stderr, run.sum_abs = tot[0], tot[1], tot[2], tot[3]
+        run.n_samples, run.n_cubes = int(cnt[0]), int(cnt[1])
+        for l in range(L.oracle_run_levels(h)):
+            n = int(L.oracle_level_n(h, l))
+            st = (C.c_double * 4)()
+            cc = (C.c_int64 * 3)()
+            L.oracle_level_stats(h, l, st, cc)
+
+            def arr(fn, count, dt):
+                ptr = fn(h, l)
+                if count == 0 or not ptr:
+                    return np.zeros(0, dtype=dt)
+                return np.ctypeslib.as_array(ptr, shape=(count,)).astype(dt, copy=True)
+
+            run.levels.append(Level(
+                n=n,
+                uid=arr(L.oracle_level_uid, n, np.uint64),
+                m=arr(L.oracle_level_m, n, np.float64),
+                s=arr(L.oracle_level_s, n, np.float64),
+                I=arr(L.oracle_level_I, n * p.trials, np.float64).reshape(n, p.trials),
+                sa=arr(L.oracle_level_sa, n, np.float64),
+                sel=arr(L.oracle_level_sel, n, np.uint8),
+                thr=st[0], mu=st[1], sd=st[2], min_margin=st[3],
+                n_sel=int(cc[0]), n_in_band=int(cc[1]), n_replayed=int(cc[2])))
+        return run
+    finally:
+        L.oracle_free(h)

@@ -1,0 +1,125 @@
+"""Statistical pins of the oracle's estimator against closed forms and brute force.
+
+A plausible slip anywhere in the sampling path (wrong edge length, volume,
+offset, axis order, dropped term in an integrand) moves the estimate by many
+standard errors; these tests would catch it.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import closed_forms as cf
+
+# (integrand id, dim, lower, upper, params) -- asymmetric boxes and parameters
+# so that an axis swap or a mirrored cube changes the answer
+CASES = [
+    ("gauss", 0, 3, [-1.0, -0.5, 0.0], [1.0, 1.5, 0.5], [0.4, 2.0, 0.1, 0.3, 0.2]),
+    ("sin_sum", 1, 3, [0.0, 1.0, -2.0], [2.0, 1.5, 3.0], []),
+    ("genz_osc", 2, 4, [0.0] * 4, [1.0] * 4, [0.3, 1.0, 2.5, 0.7, 4.0]),
+    ("genz_ppeak", 3, 3, [0.0] * 3, [1.0] * 3, [2.0, 4.0, 1.0, 0.2, 0.7, 0.9]),
+    ("genz_cpeak", 4, 3, [0.0] * 3, [1.0] * 3, [0.9, 2.0, 3.5]),
+    ("genz_gauss", 5, 4, [0.0] * 4, [1.0] * 4, [1.0, 3.0, 0.5, 2.0, 0.2, 0.8, 0.5, 0.1]),
+    ("monomial", 7, 3, [0.0, -1.0, 0.5], [1.0, 2.0, 1.5], [1.0, 2.0, 3.0]),
+]
+
+
+@pytest.mark.parametrize("name,ident,D,lo,hi,prm", CASES, ids=[c[0] for c in CASES])
+def test_integral_matches_closed_form(orc, name, ident, D, lo, hi, prm):
+    p = orc.problem(ident, D, lo, hi, 3, 1024, 5, 2, 1.0, 12345, params=prm)
+    r = orc.integrate(p)
+    assert r.status == 0
+    exact = cf.exact(ident, prm, lo, hi)
+    assert abs(r.integral - exact) <= 5.0 * r.stderr + 1e-12 * abs(exact), (r.integral, exact, r.stderr)
+    # the error estimate is of the right size (not absurdly large either)
+    assert r.stderr < 0.05 * max(abs(exact), r.sum_abs)
+
+
+@pytest.mark.parametrize("name,ident,D,lo,hi,prm", CASES[:3], ids=[c[0] for c in CASES[:3]])
+def test_per_cube_means_match_closed_form(orc, name, ident, D, lo, hi, prm):
+    p = orc.problem(ident, D, lo, hi, 2, 2048, 5, 0, 1.0, 7, params=prm)
+    for uid in range(2**D):
+        st, I, m, s, sa = orc.cube(p, 0, uid)
+        assert st == 0
+        clo, h, _ = orc.bounds(p, 0, uid)
+        exact = cf.exact(ident, prm, clo, clo + h)
+        # s is the population std of n1 trials: std error of m is s/sqrt(n1-1)
+        assert abs(m - exact) <= 6.0 * s / math.sqrt(4) + 1e-13, (uid, m, exact, s)
+        assert np.mean(I) == pytest.approx(m, rel=1e-14, abs=1e-300)
+
+
+def test_z_scores_over_seeds(orc):
+    # 20 seeds: z = (I - exact)/stderr should look standard normal
+    lo, hi, prm = [0.0] * 3, [1.0] * 3, [2.0, 4.0, 1.0, 0.2, 0.7, 0.9]
+    exact = cf.exact(3, prm, lo, hi)
+    z = []
+    for seed in range(1, 21):
+        p = orc.problem(3, 3, lo, hi, 2, 512, 5, 1, 1.0, seed, params=prm)
+        r = orc.integrate(p)
+        z.append((r.integral - exact) / r.stderr)
+    z = np.array(z)
+    assert abs(z.mean()) < 3.0 / math.sqrt(len(z)) + 0.3
+    assert 0.4 < z.std() < 2.0
+
+
+def test_constant_integrand_is_exact(orc):
+    # zero variance: every trial is A*V exactly, nothing is split, integral exact
+    p = orc.problem(orc.CONST, 4, -1.0, 1.0, 4, 4096, 5, 3, 1.0, 1, params=[1.5])
+    r = orc.integrate(p)
+    assert r.status == 0 and r.flags == 0
+    assert len(r.levels) == 1 and r.levels[0].n_sel == 0 and r.levels[0].thr == 0.0
+    assert np.all(r.levels[0].s == 0.0)
+    assert np.all(r.levels[0].I == 1.5 * 0.5**4)
+    assert r.integral == 1.5 * 16.0 and r.std == 0.0
+
+
+def _riemann_2d(fun, lo, hi, n=4096):
+    xs = [lo[i] + (np.arange(n) + 0.5) * (hi[i] - lo[i]) / n for i in range(2)]
+    X, Y = np.meshgrid(xs[0], xs[1], indexing="ij")
+    return fun(X, Y).sum() * (hi[0] - lo[0]) * (hi[1] - lo[1]) / n**2
+
+
+def test_riemann_2d_gauss(orc):
+    # brute-force midpoint sum with 4096^2 points (error ~1e-8) vs the whole tree
+    lo, hi = [-1.0, -0.5], [1.0, 1.5]
+    prm = [0.3, 1.7, 0.2, 0.4]
+    ref = _riemann_2d(lambda x, y: 1.7 * np.exp(-((x - 0.2) ** 2 + (y - 0.4) ** 2) / (2 * 0.09)), lo, hi)
+    p = orc.problem(orc.GAUSS, 2, lo, hi, 4, 4096, 5, 2, 1.0, 99, params=prm)
+    r = orc.integrate(p)
+    assert abs(r.integral - ref) <= 5 * r.stderr
+    assert r.stderr < 1e-3
+
+
+def test_riemann_2d_ppeak_per_cube(orc):
+    # per root cube: the estimator's mean vs a midpoint sum over that cube only
+    prm = [3.0, 1.5, 0.8, 0.3]
+    fun = lambda x, y: 1.0 / ((1 / 9.0 + (x - 0.8) ** 2) * (1 / 2.25 + (y - 0.3) ** 2))
+    p = orc.problem(orc.GENZ_PPEAK, 2, 0.0, 1.0, 3, 8192, 5, 0, 1.0, 5, params=prm)
+    for uid in range(9):
+        st, I, m, s, sa = orc.cube(p, 0, uid)
+        clo, h, _ = orc.bounds(p, 0, uid)
+        ref = _riemann_2d(fun, clo, clo + h, n=1024)
+        assert abs(m - ref) <= 6 * s / 2.0 + 1e-9, (uid, m, ref, s)
+
+
+def test_paper_anchor_f1(orc):
+    # f1 = sin(sum x) over [0,10]^6 (Sec. 3): the exact value lies within the
+    # spread of every result the paper prints in Tables 1 and 3
+    exact = cf.f1_exact()
+    assert exact == pytest.approx(-49.16507381641946, rel=1e-14)
+    import os
+    rows = [l.split() for l in open(os.path.join(os.path.dirname(__file__), "golden", "paper_anchors.txt"))
+            if l.strip() and not l.startswith("#")]
+    for integ, table, name, res, sd in rows:
+        want = exact if integ == "f1" else 1.0
+        assert abs(float(res) - want) <= 3.0 * float(sd), name
+    # a reduced oracle run of f1 agrees with the exact value
+    p = orc.problem(orc.SIN_SUM, 6, 0.0, 10.0, 3, 256, 5, 1, 1.0, 1)
+    r = orc.integrate(p)
+    assert abs(r.integral - exact) <= 5 * r.stderr
+
+
+def test_paper_anchor_f2(orc):
+    # normalised f2 (sigma = 0.01, 9-D, [-1,1]^9) integrates to 1 (Sec. 3)
+    A = (2 * math.pi) ** -4.5 / 0.01**9
+    assert cf.gauss(0.01, A, [0.0] * 9, [-1.0] * 9, [1.0] * 9) == pytest.approx(1.0, rel=1e-12)
