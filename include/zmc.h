@@ -1,0 +1,268 @@
+/*
+ * zmc.h -- C ABI of the MI355X (gfx950) stratified-sampling + heuristic
+ * tree-search Monte Carlo integrator.
+ *
+ * Method: "ZMCintegral: a Package for Multi-Dimensional Monte Carlo
+ * Integration on Multi-GPUs" (Wu, Zhang, Pang, Wang; arXiv:1902.07916),
+ * Sec. 2.1 (stratified sampling and heuristic tree search), Sec. 2.2
+ * (random numbers produced at the time of use), Sec. 2.3 (user parameters).
+ *
+ *  1. The domain [lower, upper] is divided into k = d^D equal hypercubes
+ *     (root cubes, level 0), numbered in row-major order, axis 0 most
+ *     significant.
+ *  2. In every cube, `trials` (the paper's n1) independent direct Monte Carlo
+ *     estimates I_t = V * mean_s f(x_s) are formed, each from
+ *     `samples_per_cube` points.  Point s, dimension i of trial t in the cube
+ *     (uid, level) uses word n = s*D + i of the Philox4x32-10 stream with key
+ *     = seed and counter (n >> 2, t | level << 8, lo32(uid), hi32(uid)), lane
+ *     n & 3; the word w maps to u = (2*(w >> 9) + 1) * 2^-24 and
+ *     x_i = fma(h_i, u, lo_i).
+ *  3. Per cube: m = mean of the I_t, s = population std of the I_t.
+ *  4. Per level and per integral: thr = mean(s) + sigma_mult * std(s)
+ *     (population std); a cube with s > thr is split (unless the level is
+ *     max_depth), all other cubes are accepted with their m.
+ *  5. A split cube is replaced by its 2^D children (every axis bisected);
+ *     child c of uid has uid' = (uid << D) | c, bit (D-1-i) of c choosing the
+ *     upper half of axis i.  The same estimate is run on the new list.
+ *  6. Result: integral = sum of accepted m; std = sqrt(sum of accepted s^2);
+ *     stderr = sqrt(sum s^2 / (n1 - 1)).
+ *
+ * Conventions for every function:
+ *  - return value: ZMC_OK (0) or a negative zmc_status; no exception or
+ *    signal crosses the ABI; zmc_strerror() describes the last error of the
+ *    calling thread;
+ *  - host pointers are read (and copied where kept) during the call; the
+ *    caller keeps ownership of everything it passes in;
+ *  - device memory is used only from the arena handed to zmc_init(); the
+ *    library never allocates or frees device memory itself (it allocates
+ *    pinned host staging buffers);
+ *  - `stream` is a hipStream_t owned by the caller (NULL = the default
+ *    stream); the library enqueues on it and, for synchronous calls,
+ *    synchronises it before returning.
+ */
+#ifndef ZMC_H
+#define ZMC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ZMC_MAX_DIM 16
+#define ZMC_MAX_LEVELS 16
+#define ZMC_MAX_PARAMS (2 * ZMC_MAX_DIM + 2)
+
+typedef enum {
+    ZMC_OK = 0,
+    ZMC_EINVAL = -1,      /* an argument is out of range (list below)          */
+    ZMC_ENOMEM = -2,      /* the arena cannot hold a level of the tree         */
+    ZMC_ENONFINITE = -3,  /* the integrand produced a NaN or an infinity       */
+    ZMC_EDEVICE = -4,     /* a HIP call failed; zmc_strerror() has its text    */
+    ZMC_EAGAIN = -5,      /* zmc_poll: the request is not finished yet         */
+    ZMC_EBUSY = -6,       /* zmc_submit: the request queue is full             */
+    ZMC_ENOINIT = -7,     /* zmc_init() has not been called                    */
+    ZMC_ECANCELED = -8,   /* the request was cancelled                         */
+    ZMC_ENOTFOUND = -9    /* unknown ticket                                    */
+} zmc_status;
+
+/* Integrand registry.  params layout (FP64; length n_params must match):
+ *  ZMC_GAUSS       [sigma, A, mu_1..mu_D]  A exp(-sum (x_i-mu_i)^2 / (2 sigma^2))
+ *                  (the paper's f2, Sec. 3, is sigma = 0.01,
+ *                   A = (sqrt(2 pi) sigma)^-9, mu = 0)
+ *  ZMC_SIN_SUM     []                      sin(sum x_i)   (the paper's f1, Sec. 3)
+ *  ZMC_GENZ_OSC    [u, c_1..c_D]           cos(2 pi u + sum c_i x_i)
+ *  ZMC_GENZ_PPEAK  [c_1..c_D, w_1..w_D]    prod 1 / (c_i^-2 + (x_i - w_i)^2)
+ *  ZMC_GENZ_CPEAK  [c_1..c_D]              (1 + sum c_i x_i)^-(D+1)
+ *  ZMC_GENZ_GAUSS  [c_1..c_D, w_1..w_D]    exp(-sum c_i^2 (x_i - w_i)^2)
+ *  ZMC_CONST       [A]                     A
+ *  ZMC_MONOMIAL    [p_1..p_D]              prod x_i^p_i, integers 0 <= p_i <= 16 */
+typedef enum {
+    ZMC_GAUSS = 0,
+    ZMC_SIN_SUM = 1,
+    ZMC_GENZ_OSC = 2,
+    ZMC_GENZ_PPEAK = 3,
+    ZMC_GENZ_CPEAK = 4,
+    ZMC_GENZ_GAUSS = 5,
+    ZMC_CONST = 6,
+    ZMC_MONOMIAL = 7
+} zmc_integrand;
+
+/* Arithmetic of the integrand evaluation.  Sums over samples, the per-cube
+ * mean/std, the threshold and every total are FP64 in both modes.
+ *  ZMC_EVAL_FP64: x and f in FP64; x is bitwise the value of step 2 above.
+ *  ZMC_EVAL_FP32: x and f in FP32 using cube-relative coordinates (offsets
+ *                 and phases formed in FP64 per cube) and the hardware
+ *                 transcendental units. */
+typedef enum { ZMC_EVAL_FP64 = 0, ZMC_EVAL_FP32 = 1 } zmc_eval;
+
+/* result.flags */
+#define ZMC_F_TRUNCATED 1 /* a level would have exceeded max_cubes_per_level:
+                             the cubes selected there were accepted instead */
+#define ZMC_F_RTOL_MET 2  /* the search stopped because stderr <= rtol*|I|  */
+
+typedef struct {
+    double integral;   /* sum of accepted per-cube means                     */
+    double std;        /* sqrt(sum of accepted s^2)                          */
+    double stderr_;    /* sqrt(sum of accepted s^2 / (trials - 1))           */
+    uint64_t n_samples;/* every evaluated point: sum_levels cubes*trials*N   */
+    uint64_t n_cubes;  /* cubes evaluated over all levels                    */
+    int32_t levels_run;
+    int32_t flags;     /* ZMC_F_*                                            */
+    int32_t status;    /* ZMC_OK or the request's zmc_status                 */
+    int32_t reserved;
+    uint64_t cubes_per_level[ZMC_MAX_LEVELS];
+    uint64_t selected_per_level[ZMC_MAX_LEVELS];
+    double thr_per_level[ZMC_MAX_LEVELS];        /* NaN where none was formed  */
+    double min_margin_per_level[ZMC_MAX_LEVELS]; /* min |s - thr| / thr        */
+    float ms_per_level[ZMC_MAX_LEVELS];          /* wall time of each level    */
+    float sample_ms_per_level[ZMC_MAX_LEVELS];   /* GPU time of the level's
+                                                    sampling launches (HIP
+                                                    events on the stream)      */
+    int32_t sample_launches_per_level[ZMC_MAX_LEVELS];
+    double latency_ms; /* serving: submit -> completion; otherwise call time */
+} zmc_result;
+
+/* One integration request: the arguments of zmc_integrate() as a struct, for
+ * zmc_integrate_batch() and zmc_submit(). */
+typedef struct {
+    int32_t integrand;           /* zmc_integrand                                */
+    int32_t dim;                 /* D, 1..16                                     */
+    int32_t divisions_per_axis;  /* d >= 1: k = d^D root cubes                   */
+    int32_t trials;              /* n1, 2..255                                   */
+    int32_t max_depth;           /* refinement rounds after level 0, 0..15       */
+    int32_t eval;                /* zmc_eval                                     */
+    int32_t n_params;
+    int32_t reserved;
+    int64_t samples_per_cube;    /* N >= 1 points per trial, N * D <= 2^34       */
+    int64_t max_cubes_per_level; /* 0 = default (2^24)                           */
+    double sigma_mult;           /* >= 0                                         */
+    double rtol;                 /* 0 = off; else stop once stderr <= rtol*|I|   */
+    uint64_t seed;               /* Philox key                                   */
+    double lower[ZMC_MAX_DIM];
+    double upper[ZMC_MAX_DIM];
+    double params[ZMC_MAX_PARAMS];
+} zmc_request;
+
+/* Library configuration. */
+typedef struct {
+    void* arena;            /* device memory, >= 64 MiB, 256-byte aligned;
+                               owned by the caller and never freed here       */
+    uint64_t arena_bytes;
+    int32_t max_slots;      /* integrals resident at once (batch / serving);
+                               0 = default 8192                               */
+    int32_t queue_depth;    /* zmc_submit queue capacity; 0 = default 65536   */
+    void* serve_stream;     /* hipStream_t used by the serving thread; NULL =
+                               serving disabled                               */
+    const char* tune_path;  /* JSON tile table written by the autotuner; NULL
+                               or "" = built-in defaults                      */
+} zmc_config;
+
+/* Per-level trace of a synchronous integration (test and debugging hook).
+ * For every level l < max_levels the library copies up to `capacity`
+ * entries, in list order, into the caller's host buffers (any may be NULL):
+ * uid[l][c], m[l][c], s[l][c], sel[l][c] (1 = split) and, per trial,
+ * S1[l][c*trials + t] = sum f and S2[l][c*trials + t] = sum f^2.
+ * n[l] receives the number of cubes at level l (even if > capacity). */
+typedef struct {
+    int32_t max_levels;
+    int32_t reserved;
+    int64_t capacity;
+    int64_t n[ZMC_MAX_LEVELS];
+    uint64_t* uid[ZMC_MAX_LEVELS];
+    double* m[ZMC_MAX_LEVELS];
+    double* s[ZMC_MAX_LEVELS];
+    uint8_t* sel[ZMC_MAX_LEVELS];
+    double* S1[ZMC_MAX_LEVELS];
+    double* S2[ZMC_MAX_LEVELS];
+} zmc_trace;
+
+/* Initialise the library on the current HIP device with the caller's arena.
+ * EINVAL: NULL cfg/arena, arena_bytes < 64 MiB, misaligned arena.
+ * Calling it again after zmc_shutdown() is allowed. */
+int zmc_init(const zmc_config* cfg);
+
+/* Stop the serving thread (pending tickets end with ZMC_ECANCELED), release
+ * host staging memory.  The arena is not touched. */
+int zmc_shutdown(void);
+
+/* Integrate one function (Sec. 2.1 steps 1-6 above), synchronously.
+ * params: n_params FP64 values (layout per zmc_integrand); lower/upper: dim
+ * FP64 values each; out: caller memory, valid when ZMC_OK is returned (and
+ * filled with status on ZMC_ENONFINITE / ZMC_ENOMEM).
+ * EINVAL when: dim not in 1..16; lower_i >= upper_i or not finite; d < 1;
+ * N < 1 or N*D > 2^34; trials not in 2..255; max_depth not in 0..15;
+ * sigma_mult < 0 or not finite; unknown integrand or wrong n_params; a
+ * MONOMIAL exponent outside 0..16 or not an integer; ceil(log2(d^D)) +
+ * D*max_depth > 64 (uid overflow); d^D > max_cubes_per_level.
+ * ENOMEM when a level does not fit the arena. */
+int zmc_integrate(int integrand_id, const double* params, int n_params, int dim, const double* lower,
+                  const double* upper, int divisions_per_axis, int64_t samples_per_cube, int trials,
+                  int max_depth, double sigma_mult, uint64_t seed, int eval, void* stream, zmc_result* out);
+
+/* zmc_integrate() with every field of zmc_request (rtol, level cap) and an
+ * optional trace (NULL = none). */
+int zmc_integrate_request(const zmc_request* req, void* stream, zmc_result* out, zmc_trace* trace);
+
+/* Integrate n independent requests together (each with its own threshold per
+ * level): all their cubes are evaluated by the same launches, level by level.
+ * outs[i] receives request i's result; each result is bitwise the one
+ * zmc_integrate_request() returns for that request alone.  Returns ZMC_OK if
+ * the batch ran (per-request failures are in outs[i].status), EINVAL if n <
+ * 1, n > max_slots or any request is invalid, ENOMEM if the arena cannot
+ * hold the batch's first level. */
+int zmc_integrate_batch(const zmc_request* reqs, int n, void* stream, zmc_result* outs);
+
+/* Serving (continuous batching at level granularity): enqueue a copy of req
+ * and return a ticket.  The serving thread admits queued requests whenever
+ * slots and arena memory allow, runs every resident request's current level
+ * in shared launches, and retires finished requests.  EINVAL: invalid
+ * request; EBUSY: queue full; ENOINIT: no serve_stream was configured. */
+int zmc_submit(const zmc_request* req, uint64_t* ticket);
+
+/* Result of a ticket.  wait = 0: returns EAGAIN while it runs; wait != 0:
+ * blocks until done.  On completion the result (with its own status) is
+ * copied to out, the ticket is released and ZMC_OK is returned; ENOTFOUND
+ * for an unknown or already-collected ticket. */
+int zmc_poll(uint64_t ticket, zmc_result* out, int wait);
+
+/* Cancel a queued or running request; its poll then returns a result with
+ * status ECANCELED.  ENOTFOUND for unknown tickets. */
+int zmc_cancel(uint64_t ticket);
+
+/* Serving counters: queued, resident, completed, levels stepped. */
+int zmc_serve_stats(uint64_t out4[4]);
+
+/* Evaluate Philox4x32-10 on the device for n counters (key = (key_lo,
+ * key_hi) for all): ctr is n*4 u32 (host), out n*4 u32 (host).  The same
+ * device function the sampling kernels use. */
+int zmc_debug_philox(uint32_t key_lo, uint32_t key_hi, const uint32_t* ctr, int64_t n, uint32_t* out,
+                     void* stream);
+
+/* Device sample points: for cube (uid, level) of req, trial t, samples
+ * s0 .. s0+n-1, write x (n*D FP64, host) exactly as the FP64 path forms them. */
+int zmc_debug_points(const zmc_request* req, int level, uint64_t uid, int trial, int64_t s0, int64_t n,
+                     double* x, void* stream);
+
+/* Per-cube estimates for an explicit list of cubes (all at `level`) of one
+ * request: the sampling and per-cube reduction kernels of zmc_integrate run
+ * on uids[0..n) (host array) and write m[n], s[n] and, if non-NULL,
+ * S1[n*trials], S2[n*trials] (host arrays). */
+int zmc_cube_estimates(const zmc_request* req, int level, const uint64_t* uids, int64_t n, double* m,
+                       double* s, double* S1, double* S2, void* stream);
+
+/* Text for a status code, or the last HIP error text for ZMC_EDEVICE. */
+const char* zmc_strerror(int status);
+
+/* Version string of the library build. */
+const char* zmc_version(void);
+
+/* sizeof of the ABI structs, for bindings that mirror them: which = 0
+ * zmc_result, 1 zmc_request, 2 zmc_config, 3 zmc_trace; -1 otherwise. */
+int zmc_struct_size(int which);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZMC_H */

@@ -138,7 +138,8 @@ uint32_t oracle_word(uint64_t seed, uint64_t uid, int level, int trial, int dim,
  * axis on a grid of d * 2^level cells. */
 void oracle_cube_lattice(int dim, int divisions, int level, uint64_t uid, uint64_t* K)
 {
-    uint64_t root = (level > 0) ? (uid >> (uint64_t)(dim * level)) : uid;
+    /* the root index sits above the D*level path bits (none left at 64) */
+    uint64_t root = (dim * level >= 64) ? 0 : (uid >> (uint64_t)(dim * level));
     for (int i = dim - 1; i >= 0; --i) {
         K[i] = root % (uint64_t)divisions;
         root /= (uint64_t)divisions;

@@ -1,0 +1,494 @@
+// zmc_abi.hip -- the extern "C" entry points declared in zmc.h: argument
+// checks, the library context (arena split between the synchronous engine
+// and the serving engine), and the serving thread (continuous batching at
+// tree-level granularity).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <string.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <unordered_set>
+
+#include "zmc.h"
+#include "zmc_engine.hpp"
+
+using namespace zmc;
+
+namespace {
+
+struct Server {
+    Engine eng;
+    hipStream_t st = nullptr;
+    std::thread th;
+    std::mutex mu;
+    std::condition_variable cv_q, cv_done;
+    std::deque<HostSlot> queue;
+    size_t queue_cap = 65536;
+    std::unordered_map<uint64_t, zmc_result> done;
+    std::unordered_set<uint64_t> pending; // queued or resident
+    std::unordered_set<uint64_t> cancelled;
+    uint64_t next_ticket = 1;
+    volatile bool stop = false;
+    uint64_t n_completed = 0, n_levels = 0;
+    int resident = 0;
+    int rc = ZMC_OK;
+};
+
+struct Context {
+    bool inited = false;
+    int device = 0;
+    TileTable tiles;
+    Engine sync_eng;
+    std::mutex sync_mu;
+    Server* server = nullptr;
+};
+
+Context g;
+std::mutex g_init_mu;
+
+uint64_t ipow_sat(uint64_t b, int e, bool* ovf)
+{
+    uint64_t r = 1;
+    *ovf = false;
+    for (int i = 0; i < e; ++i) {
+        if (b != 0 && r > UINT64_MAX / b) {
+            *ovf = true;
+            return UINT64_MAX;
+        }
+        r *= b;
+    }
+    return r;
+}
+
+int n_params_of(int id, int dim)
+{
+    switch (id) {
+    case ZMC_GAUSS: return 2 + dim;
+    case ZMC_SIN_SUM: return 0;
+    case ZMC_GENZ_OSC: return 1 + dim;
+    case ZMC_GENZ_PPEAK: return 2 * dim;
+    case ZMC_GENZ_CPEAK: return dim;
+    case ZMC_GENZ_GAUSS: return 2 * dim;
+    case ZMC_CONST: return 1;
+    case ZMC_MONOMIAL: return dim;
+    default: return -1;
+    }
+}
+
+int fail(int code, const char* msg)
+{
+    set_error(msg);
+    return code;
+}
+
+// The argument rules of zmc_integrate (see zmc.h).
+int validate(const zmc_request& r)
+{
+    if (r.dim < 1 || r.dim > ZMC_MAX_DIM) return fail(ZMC_EINVAL, "dim must be in 1..16");
+    if (r.integrand < 0 || r.integrand > ZMC_MONOMIAL) return fail(ZMC_EINVAL, "unknown integrand");
+    if (r.n_params != n_params_of(r.integrand, r.dim)) return fail(ZMC_EINVAL, "wrong number of params");
+    if (r.integrand == ZMC_MONOMIAL)
+        for (int j = 0; j < r.n_params; ++j)
+            if (!(r.params[j] >= 0.0 && r.params[j] <= 16.0 && r.params[j] == floor(r.params[j])))
+                return fail(ZMC_EINVAL, "monomial exponents must be integers in 0..16");
+    if (r.eval != ZMC_EVAL_FP64 && r.eval != ZMC_EVAL_FP32) return fail(ZMC_EINVAL, "unknown eval mode");
+    if (r.divisions_per_axis < 1) return fail(ZMC_EINVAL, "divisions_per_axis must be >= 1");
+    if (r.samples_per_cube < 1) return fail(ZMC_EINVAL, "samples_per_cube must be >= 1");
+    if ((uint64_t)r.samples_per_cube * (uint64_t)r.dim > (1ull << 34))
+        return fail(ZMC_EINVAL, "samples_per_cube * dim must be <= 2^34");
+    if (r.trials < 2 || r.trials > 255) return fail(ZMC_EINVAL, "trials must be in 2..255");
+    if (r.max_depth < 0 || r.max_depth >= ZMC_MAX_LEVELS) return fail(ZMC_EINVAL, "max_depth must be in 0..15");
+    if (!isfinite(r.sigma_mult) || r.sigma_mult < 0.0) return fail(ZMC_EINVAL, "sigma_mult must be finite, >= 0");
+    if (!isfinite(r.rtol) || r.rtol < 0.0) return fail(ZMC_EINVAL, "rtol must be finite, >= 0");
+    if (r.max_cubes_per_level < 0) return fail(ZMC_EINVAL, "max_cubes_per_level must be >= 0");
+    for (int i = 0; i < r.dim; ++i)
+        if (!isfinite(r.lower[i]) || !isfinite(r.upper[i]) || !(r.lower[i] < r.upper[i]))
+            return fail(ZMC_EINVAL, "bounds must be finite with lower < upper");
+    bool ovf = false;
+    const uint64_t k = ipow_sat((uint64_t)r.divisions_per_axis, r.dim, &ovf);
+    if (ovf) return fail(ZMC_EINVAL, "d^D overflows 64 bits");
+    int root_bits = 0;
+    for (uint64_t t = k - 1; t; t >>= 1) ++root_bits;
+    if (root_bits + r.dim * r.max_depth > 64) return fail(ZMC_EINVAL, "uid would overflow 64 bits");
+    const int64_t cap = r.max_cubes_per_level > 0 ? r.max_cubes_per_level : ZMC_DEFAULT_MAX_CUBES;
+    if (k > (uint64_t)cap) return fail(ZMC_EINVAL, "d^D exceeds max_cubes_per_level");
+    return ZMC_OK;
+}
+
+zmc_request make_request(int integrand_id, const double* params, int n_params, int dim, const double* lower,
+                         const double* upper, int d, int64_t N, int trials, int max_depth, double sigma_mult,
+                         uint64_t seed, int eval)
+{
+    zmc_request r;
+    memset(&r, 0, sizeof(r));
+    r.integrand = integrand_id;
+    r.dim = dim;
+    r.divisions_per_axis = d;
+    r.trials = trials;
+    r.max_depth = max_depth;
+    r.eval = eval;
+    r.n_params = n_params;
+    r.samples_per_cube = N;
+    r.sigma_mult = sigma_mult;
+    r.seed = seed;
+    for (int i = 0; i < dim && i < ZMC_MAX_DIM; ++i) {
+        r.lower[i] = lower ? lower[i] : NAN;
+        r.upper[i] = upper ? upper[i] : NAN;
+    }
+    for (int j = 0; j < n_params && j < ZMC_MAX_PARAMS; ++j) r.params[j] = params ? params[j] : NAN;
+    if (n_params > ZMC_MAX_PARAMS || n_params < 0) r.n_params = -1;
+    return r;
+}
+
+void init_result(zmc_result& R)
+{
+    memset(&R, 0, sizeof(R));
+    for (int l = 0; l < ZMC_MAX_LEVELS; ++l) {
+        R.thr_per_level[l] = NAN;
+        R.min_margin_per_level[l] = NAN;
+    }
+    R.integral = R.std = R.stderr_ = NAN;
+}
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+void server_main(Server* S, int device)
+{
+    (void)hipSetDevice(device);
+    Engine::Admission adm;
+    adm.admit = [S](std::vector<HostSlot>& out, int free_slots, size_t budget, bool idle) {
+        std::unique_lock<std::mutex> lk(S->mu);
+        if (idle) {
+            while (S->queue.empty() && !S->stop) S->cv_q.wait_for(lk, std::chrono::milliseconds(20));
+        }
+        while (!S->queue.empty() && free_slots > 0) {
+            HostSlot& hs = S->queue.front();
+            if (S->cancelled.count(hs.ticket)) {
+                zmc_result R;
+                init_result(R);
+                R.status = ZMC_ECANCELED;
+                S->done[hs.ticket] = R;
+                S->pending.erase(hs.ticket);
+                S->cancelled.erase(hs.ticket);
+                S->queue.pop_front();
+                S->cv_done.notify_all();
+                continue;
+            }
+            if (hs.reserve > S->eng.budget_bytes()) {
+                zmc_result R;
+                init_result(R);
+                R.status = ZMC_ENOMEM;
+                S->done[hs.ticket] = R;
+                S->pending.erase(hs.ticket);
+                S->queue.pop_front();
+                S->cv_done.notify_all();
+                continue;
+            }
+            if (hs.reserve > budget) break; // wait for memory to free up
+            budget -= hs.reserve;
+            --free_slots;
+            out.push_back(hs);
+            S->queue.pop_front();
+            ++S->resident;
+        }
+        return !S->stop;
+    };
+    adm.retire = [S](HostSlot& hs) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        hs.res.latency_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - hs.t_submit).count();
+        if (S->cancelled.count(hs.ticket)) {
+            hs.res.status = ZMC_ECANCELED;
+            S->cancelled.erase(hs.ticket);
+        }
+        S->done[hs.ticket] = hs.res;
+        S->pending.erase(hs.ticket);
+        ++S->n_completed;
+        --S->resident;
+        S->cv_done.notify_all();
+    };
+    adm.cancelled = [S](uint64_t t) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        return S->cancelled.count(t) > 0;
+    };
+    int rc = S->eng.drive(S->st, adm, nullptr, &S->stop, &S->n_levels);
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->rc = rc;
+    // anything still queued ends cancelled
+    for (HostSlot& hs : S->queue) {
+        zmc_result R;
+        init_result(R);
+        R.status = ZMC_ECANCELED;
+        S->done[hs.ticket] = R;
+        S->pending.erase(hs.ticket);
+    }
+    S->queue.clear();
+    S->cv_done.notify_all();
+}
+
+void stop_server()
+{
+    Server* S = g.server;
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+        S->cv_q.notify_all();
+    }
+    if (S->th.joinable()) S->th.join();
+    S->eng.teardown();
+    delete S;
+    g.server = nullptr;
+}
+
+} // namespace
+
+extern "C" {
+
+int zmc_init(const zmc_config* cfg)
+{
+    std::lock_guard<std::mutex> lk(g_init_mu);
+    if (!cfg || !cfg->arena) return fail(ZMC_EINVAL, "zmc_init: NULL config or arena");
+    if (cfg->arena_bytes < (64ull << 20)) return fail(ZMC_EINVAL, "zmc_init: arena must be >= 64 MiB");
+    if (((uintptr_t)cfg->arena & 255) != 0) return fail(ZMC_EINVAL, "zmc_init: arena must be 256-byte aligned");
+    if (g.inited) {
+        stop_server();
+        g.sync_eng.teardown();
+        g.inited = false;
+    }
+    if (hipGetDevice(&g.device) != hipSuccess) return fail(ZMC_EDEVICE, "hipGetDevice failed");
+    g.tiles = TileTable();
+    if (cfg->tune_path && cfg->tune_path[0]) {
+        if (g.tiles.load(cfg->tune_path) != 0) return fail(ZMC_EINVAL, "zmc_init: cannot read tune_path");
+    }
+    const int slots = cfg->max_slots > 0 ? cfg->max_slots : 8192;
+    char* base = (char*)cfg->arena;
+    size_t bytes = (size_t)cfg->arena_bytes;
+    size_t sync_bytes = bytes;
+    if (cfg->serve_stream) sync_bytes = (bytes / 4) & ~(size_t)255;
+    int rc = g.sync_eng.setup(base, sync_bytes, slots, &g.tiles, g.device);
+    if (rc != ZMC_OK) return rc;
+    if (cfg->serve_stream) {
+        Server* S = new Server();
+        S->st = (hipStream_t)cfg->serve_stream;
+        S->queue_cap = cfg->queue_depth > 0 ? (size_t)cfg->queue_depth : 65536;
+        rc = S->eng.setup(base + sync_bytes, bytes - sync_bytes, slots, &g.tiles, g.device);
+        if (rc != ZMC_OK) {
+            delete S;
+            g.sync_eng.teardown();
+            return rc;
+        }
+        g.server = S;
+        S->th = std::thread(server_main, S, g.device);
+    }
+    g.inited = true;
+    return ZMC_OK;
+}
+
+int zmc_shutdown(void)
+{
+    std::lock_guard<std::mutex> lk(g_init_mu);
+    if (!g.inited) return ZMC_OK;
+    stop_server();
+    {
+        std::lock_guard<std::mutex> lk2(g.sync_mu);
+        g.sync_eng.teardown();
+    }
+    g.inited = false;
+    return ZMC_OK;
+}
+
+int zmc_integrate_request(const zmc_request* req, void* stream, zmc_result* out, zmc_trace* trace)
+{
+    if (!req || !out) return fail(ZMC_EINVAL, "NULL request or result");
+    init_result(*out);
+    int rc = validate(*req);
+    if (rc != ZMC_OK) {
+        out->status = rc;
+        return rc;
+    }
+    if (!g.inited) return fail(ZMC_ENOINIT, "zmc_init has not been called");
+    std::lock_guard<std::mutex> lk(g.sync_mu);
+    rc = g.sync_eng.run(req, 1, (hipStream_t)stream, out, trace);
+    if (rc == ZMC_OK && out->status != ZMC_OK) rc = out->status;
+    return rc;
+}
+
+int zmc_integrate(int integrand_id, const double* params, int n_params, int dim, const double* lower,
+                  const double* upper, int divisions_per_axis, int64_t samples_per_cube, int trials, int max_depth,
+                  double sigma_mult, uint64_t seed, int eval, void* stream, zmc_result* out)
+{
+    if ((n_params > 0 && !params) || !lower || !upper) return fail(ZMC_EINVAL, "NULL params or bounds");
+    const zmc_request r = make_request(integrand_id, params, n_params, dim, lower, upper, divisions_per_axis,
+                                       samples_per_cube, trials, max_depth, sigma_mult, seed, eval);
+    return zmc_integrate_request(&r, stream, out, nullptr);
+}
+
+int zmc_integrate_batch(const zmc_request* reqs, int n, void* stream, zmc_result* outs)
+{
+    if (!reqs || !outs || n < 1) return fail(ZMC_EINVAL, "empty batch");
+    for (int i = 0; i < n; ++i) {
+        init_result(outs[i]);
+        const int rc = validate(reqs[i]);
+        if (rc != ZMC_OK) {
+            outs[i].status = rc;
+            return rc;
+        }
+    }
+    if (!g.inited) return fail(ZMC_ENOINIT, "zmc_init has not been called");
+    std::lock_guard<std::mutex> lk(g.sync_mu);
+    return g.sync_eng.run(reqs, n, (hipStream_t)stream, outs, nullptr);
+}
+
+int zmc_submit(const zmc_request* req, uint64_t* ticket)
+{
+    if (!req || !ticket) return fail(ZMC_EINVAL, "NULL request or ticket");
+    const int rc = validate(*req);
+    if (rc != ZMC_OK) return rc;
+    if (!g.inited || !g.server) return fail(ZMC_ENOINIT, "serving is not configured");
+    Server* S = g.server;
+    HostSlot hs;
+    hs.req = *req;
+    init_result(hs.res);
+    hs.reserve = S->eng.reservation_bytes(*req);
+    hs.t_submit = std::chrono::steady_clock::now();
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (S->queue.size() >= S->queue_cap) return fail(ZMC_EBUSY, "request queue is full");
+    hs.ticket = S->next_ticket++;
+    S->pending.insert(hs.ticket);
+    S->queue.push_back(hs);
+    *ticket = hs.ticket;
+    S->cv_q.notify_all();
+    return ZMC_OK;
+}
+
+int zmc_poll(uint64_t ticket, zmc_result* out, int wait)
+{
+    if (!out) return fail(ZMC_EINVAL, "NULL result");
+    if (!g.inited || !g.server) return fail(ZMC_ENOINIT, "serving is not configured");
+    Server* S = g.server;
+    std::unique_lock<std::mutex> lk(S->mu);
+    while (true) {
+        auto it = S->done.find(ticket);
+        if (it != S->done.end()) {
+            *out = it->second;
+            S->done.erase(it);
+            return ZMC_OK;
+        }
+        if (!S->pending.count(ticket)) return fail(ZMC_ENOTFOUND, "unknown ticket");
+        if (!wait) return ZMC_EAGAIN;
+        S->cv_done.wait_for(lk, std::chrono::milliseconds(50));
+    }
+}
+
+int zmc_cancel(uint64_t ticket)
+{
+    if (!g.inited || !g.server) return fail(ZMC_ENOINIT, "serving is not configured");
+    Server* S = g.server;
+    std::lock_guard<std::mutex> lk(S->mu);
+    if (!S->pending.count(ticket)) return fail(ZMC_ENOTFOUND, "unknown ticket");
+    for (auto it = S->queue.begin(); it != S->queue.end(); ++it) {
+        if (it->ticket == ticket) {
+            zmc_result R;
+            init_result(R);
+            R.status = ZMC_ECANCELED;
+            S->done[ticket] = R;
+            S->pending.erase(ticket);
+            S->queue.erase(it);
+            S->cv_done.notify_all();
+            return ZMC_OK;
+        }
+    }
+    S->cancelled.insert(ticket);
+    return ZMC_OK;
+}
+
+int zmc_serve_stats(uint64_t out4[4])
+{
+    if (!out4) return fail(ZMC_EINVAL, "NULL output");
+    if (!g.inited || !g.server) return fail(ZMC_ENOINIT, "serving is not configured");
+    Server* S = g.server;
+    std::lock_guard<std::mutex> lk(S->mu);
+    out4[0] = S->queue.size();
+    out4[1] = (uint64_t)S->resident;
+    out4[2] = S->n_completed;
+    out4[3] = S->n_levels;
+    return ZMC_OK;
+}
+
+int zmc_debug_philox(uint32_t key_lo, uint32_t key_hi, const uint32_t* ctr, int64_t n, uint32_t* out, void* stream)
+{
+    if (!ctr || !out || n < 0) return fail(ZMC_EINVAL, "bad debug_philox arguments");
+    if (!g.inited) return fail(ZMC_ENOINIT, "zmc_init has not been called");
+    if (n == 0) return ZMC_OK;
+    std::lock_guard<std::mutex> lk(g.sync_mu);
+    return g.sync_eng.debug_philox(key_lo, key_hi, ctr, n, out, (hipStream_t)stream);
+}
+
+int zmc_debug_points(const zmc_request* req, int level, uint64_t uid, int trial, int64_t s0, int64_t n, double* x,
+                     void* stream)
+{
+    if (!req || !x || n < 0 || s0 < 0 || level < 0 || level >= ZMC_MAX_LEVELS || trial < 0)
+        return fail(ZMC_EINVAL, "bad debug_points arguments");
+    int rc = validate(*req);
+    if (rc != ZMC_OK) return rc;
+    if (trial >= req->trials || s0 + n > req->samples_per_cube) return fail(ZMC_EINVAL, "sample out of range");
+    if (!g.inited) return fail(ZMC_ENOINIT, "zmc_init has not been called");
+    if (n == 0) return ZMC_OK;
+    std::lock_guard<std::mutex> lk(g.sync_mu);
+    return g.sync_eng.debug_points(*req, level, uid, trial, s0, n, x, (hipStream_t)stream);
+}
+
+int zmc_cube_estimates(const zmc_request* req, int level, const uint64_t* uids, int64_t n, double* m, double* s,
+                       double* S1, double* S2, void* stream)
+{
+    if (!req || (n > 0 && !uids) || n < 0 || level < 0 || level >= ZMC_MAX_LEVELS)
+        return fail(ZMC_EINVAL, "bad cube_estimates arguments");
+    int rc = validate(*req);
+    if (rc != ZMC_OK) return rc;
+    if (!g.inited) return fail(ZMC_ENOINIT, "zmc_init has not been called");
+    if (n == 0) return ZMC_OK;
+    std::lock_guard<std::mutex> lk(g.sync_mu);
+    return g.sync_eng.cube_estimates(*req, level, uids, n, m, s, S1, S2, (hipStream_t)stream);
+}
+
+const char* zmc_strerror(int status)
+{
+    switch (status) {
+    case ZMC_OK: return "ok";
+    case ZMC_EINVAL: return last_error()[0] ? last_error() : "invalid argument";
+    case ZMC_ENOMEM: return "arena exhausted";
+    case ZMC_ENONFINITE: return "integrand produced a non-finite value";
+    case ZMC_EDEVICE: return last_error()[0] ? last_error() : "HIP error";
+    case ZMC_EAGAIN: return "not finished";
+    case ZMC_EBUSY: return "queue full";
+    case ZMC_ENOINIT: return "not initialised";
+    case ZMC_ECANCELED: return "cancelled";
+    case ZMC_ENOTFOUND: return "unknown ticket";
+    default: return "unknown status";
+    }
+}
+
+const char* zmc_version(void) { return "zmc-mi355x 0.1 (gfx950)"; }
+
+int zmc_struct_size(int which)
+{
+    switch (which) {
+    case 0: return (int)sizeof(zmc_result);
+    case 1: return (int)sizeof(zmc_request);
+    case 2: return (int)sizeof(zmc_config);
+    case 3: return (int)sizeof(zmc_trace);
+    default: return -1;
+    }
+}
+
+} // extern "C"

@@ -1,0 +1,172 @@
+// zmc_device.hpp -- device-side building blocks of the integrator for gfx950:
+// the counter-based RNG, the uniform mapping, the sub-domain geometry, the
+// integrand registry in FP64 and in cube-relative FP32, and the shared data
+// layouts of the level pipeline.
+//
+// Method: ZMCintegral (arXiv:1902.07916), Sec. 2.1 (stratified sampling and
+// heuristic tree search) and Sec. 2.2 (random numbers produced at the time of
+// use instead of stored batches).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "zmc.h"
+
+namespace zmc {
+
+constexpr int kMaxDim = ZMC_MAX_DIM;
+constexpr int kMaxParams = ZMC_MAX_PARAMS;
+constexpr int kTileCubes = 1024;   // cubes per tile of the per-cube kernels
+constexpr int kLevelThreads = 256; // threads per block of the per-cube kernels
+
+// ---------------------------------------------------------------------------
+// Device-resident tables (structure of arrays where per-cube, small structs
+// where per-integral or per-segment).
+// ---------------------------------------------------------------------------
+
+// One integral resident on the device (read-only while resident).
+struct alignas(16) SlotDesc {
+    int32_t integrand, dim, eval, divisions;
+    int32_t trials, max_depth, nch, groups; // nch: sample chunks per trial; groups: 4-sample groups per thread per chunk
+    int64_t samples, max_cubes;
+    double sigma_mult, rtol;
+    uint64_t seed;
+    int64_t reserved;
+    double lower[kMaxDim];
+    double h0[kMaxDim]; // (upper - lower) / d, the root edge lengths
+    double params[kMaxParams];
+};
+
+// A run of consecutive cubes of the current list that belong to one integral.
+struct alignas(16) Segment {
+    int32_t slot, level;
+    int64_t cube_base, n_cubes;
+    int64_t part_base;  // index of its first (cube, trial, chunk) partial
+    int64_t tile_base;  // index of its first tile
+    int64_t n_tiles;
+    int64_t child_base; // where its children start in the next list
+    int32_t do_split;   // 1: spawn its selected cubes' children
+    int32_t need_thr;   // 1: a threshold is formed at this level
+};
+
+// Sampling work of one (integrand, D, eval) bucket: segment `seg` owns the
+// bucket-local units [unit_base, next unit_base).
+struct alignas(16) BSeg {
+    int64_t unit_base;
+    int32_t seg;
+    int32_t pad;
+};
+
+// Per-tile partial reductions of the per-cube kernels.
+struct alignas(16) TileRec {
+    double sum_s, sum_sq;
+    double accM, accS2, selM, selS2;
+    double min_margin;
+    int64_t n_sel, sel_prefix;
+    int32_t nonfinite, pad;
+};
+
+enum Decision : int32_t { kSplit = 0, kDone = 1, kTruncated = 2, kRtolMet = 3 };
+
+// Per-segment outcome of one level, read back by the host after every level.
+struct alignas(16) SegStats {
+    double mu, sd, thr, min_margin;
+    double accM, accS2, selM, selS2;
+    double totM, totS2; // running totals of the integral after this level
+    int64_t n_sel;
+    int32_t decision, nonfinite;
+};
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products
+// (constants 0xD2511F53, 0xCD9E8D57), the half-swapping S-box XORed with the
+// round key, and the Weyl key schedule (0x9E3779B9, 0xBB67AE85).  On gfx950 a
+// round is two v_mad_u64_u32 and two v_bitop3_b32 (three-input XOR, function
+// 0x96); the key schedule is wave-uniform and stays on the scalar unit.
+// ---------------------------------------------------------------------------
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+__device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                            uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
+        const uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// u = (2*(w>>9)+1) * 2^-24, exact in FP64.
+__device__ __forceinline__ double uniform_f64(uint32_t w)
+{
+    return (double)((w >> 8) | 1u) * 0x1p-24;
+}
+
+// The same cell as uniform_f64 as a float in [1, 2): 1 + (w>>9) * 2^-23, so
+// u = v - (1 - 2^-24).  One v_alignbit_b32 moves the top 23 bits of w under
+// the exponent of 1.0f.
+__device__ __forceinline__ float unit_interval_f32(uint32_t w)
+{
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, w, 9u));
+}
+
+// ---------------------------------------------------------------------------
+// Geometry of cube (uid, level): lattice cell K_i on a grid of d*2^level
+// cells per axis.  Root index r = uid >> (D*level) in row-major order with
+// axis 0 most significant; each refinement appends D bits, bit (D-1-i)
+// choosing the upper half of axis i.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void cube_corner(const SlotDesc& sd, int D, int level, uint64_t uid, double* lo,
+                                            double* h)
+{
+    uint64_t K[kMaxDim];
+    uint64_t root = (D * level >= 64) ? 0 : (uid >> (uint64_t)(D * level));
+    const uint64_t d = (uint64_t)sd.divisions;
+    if (root < (1ull << 32)) {
+        uint32_t r32 = (uint32_t)root;
+        for (int i = D - 1; i >= 0; --i) {
+            K[i] = r32 % (uint32_t)d;
+            r32 /= (uint32_t)d;
+        }
+    } else {
+        for (int i = D - 1; i >= 0; --i) {
+            K[i] = root % d;
+            root /= d;
+        }
+    }
+    const uint64_t mask = (1ull << D) - 1ull;
+    for (int j = 1; j <= level; ++j) {
+        const uint64_t c = (uid >> (uint64_t)(D * (level - j))) & mask;
+        for (int i = 0; i < D; ++i) K[i] = 2u * K[i] + ((c >> (uint64_t)(D - 1 - i)) & 1u);
+    }
+    for (int i = 0; i < D; ++i) {
+        h[i] = ldexp(sd.h0[i], -level);
+        lo[i] = fma((double)K[i], h[i], sd.lower[i]);
+    }
+}
+
+__device__ __forceinline__ double cube_volume(const SlotDesc& sd, int D, int level)
+{
+    double v = 1.0;
+    for (int i = 0; i < D; ++i) v = v * ldexp(sd.h0[i], -level);
+    return v;
+}
+
+} // namespace zmc

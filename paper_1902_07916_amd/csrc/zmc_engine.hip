@@ -1,0 +1,704 @@
+// zmc_engine.hip -- level driver: lays out each level's cube list for all
+// resident integrals, launches the level pipeline, reads back one record per
+// integral, applies the stop rules of the tree search (ZMCintegral, Sec. 2.1)
+// and builds the next level's list.
+#include "zmc_engine.hpp"
+
+#include <float.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <fstream>
+#include <sstream>
+
+namespace zmc {
+
+namespace {
+thread_local std::string g_err;
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+uint64_t ipow_u64(uint64_t b, int e)
+{
+    uint64_t r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+} // namespace
+
+void set_error(const std::string& s) { g_err = s; }
+const char* last_error() { return g_err.c_str(); }
+
+#define ZMC_HIP(call)                                                                                      \
+    do {                                                                                                   \
+        hipError_t e_ = (call);                                                                            \
+        if (e_ != hipSuccess) {                                                                            \
+            set_error(std::string(#call) + ": " + hipGetErrorString(e_));                                  \
+            return ZMC_EDEVICE;                                                                            \
+        }                                                                                                  \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+TileTable::TileTable()
+{
+    for (int f = 0; f < 8; ++f)
+        for (int d = 0; d <= ZMC_MAX_DIM; ++d)
+            for (int e = 0; e < 2; ++e) groups[f][d][e] = 4;
+}
+
+// Tuning file: a JSON object whose keys "integrand:dim:eval" map to the
+// number of 4-point groups per thread per chunk, e.g. {"1:6:1": 8}.
+int TileTable::load(const char* path)
+{
+    std::ifstream in(path);
+    if (!in) return -1;
+    std::stringstream ss;
+    ss << in.rdbuf();
+    const std::string t = ss.str();
+    size_t p = 0;
+    while ((p = t.find('"', p)) != std::string::npos) {
+        const size_t q = t.find('"', p + 1);
+        if (q == std::string::npos) break;
+        int f, d, e;
+        const std::string key = t.substr(p + 1, q - p - 1);
+        p = q + 1;
+        if (sscanf(key.c_str(), "%d:%d:%d", &f, &d, &e) != 3) continue;
+        const size_t c = t.find(':', q);
+        if (c == std::string::npos) break;
+        const int g = atoi(t.c_str() + c + 1);
+        if (f >= 0 && f < 8 && d >= 1 && d <= ZMC_MAX_DIM && e >= 0 && e < 2 && g >= 1 && g <= 64)
+            groups[f][d][e] = g;
+    }
+    return 0;
+}
+
+// ---------------------------------------------------------------------------
+int Engine::setup(char* base, size_t bytes, int max_slots, const TileTable* tiles, int device)
+{
+    region_ = base;
+    region_bytes_ = bytes;
+    max_slots_ = max_slots;
+    tiles_ = tiles;
+    device_ = device;
+    size_t off = 0;
+    auto carve = [&](size_t b) {
+        off = (off + 255) & ~(size_t)255;
+        char* p = base + off;
+        off += b;
+        return p;
+    };
+    d_slots_ = (SlotDesc*)carve(sizeof(SlotDesc) * max_slots);
+    d_segs_ = (Segment*)carve(sizeof(Segment) * max_slots);
+    d_bsegs_ = (BSeg*)carve(sizeof(BSeg) * max_slots);
+    d_stats_ = (SegStats*)carve(sizeof(SegStats) * max_slots);
+    d_prev_ = (double2*)carve(sizeof(double2) * max_slots);
+    d_rootsegs_ = (Segment*)carve(sizeof(Segment) * max_slots);
+    off = (off + 255) & ~(size_t)255;
+    if (off + (16u << 20) > bytes) {
+        set_error("arena too small for the slot tables");
+        return ZMC_EINVAL;
+    }
+    arena_.init(base + off, bytes - off);
+    ZMC_HIP(hipHostMalloc((void**)&h_slots_, sizeof(SlotDesc) * max_slots, hipHostMallocDefault));
+    ZMC_HIP(hipHostMalloc((void**)&h_segs_, sizeof(Segment) * max_slots, hipHostMallocDefault));
+    ZMC_HIP(hipHostMalloc((void**)&h_segs2_, sizeof(Segment) * max_slots, hipHostMallocDefault));
+    ZMC_HIP(hipHostMalloc((void**)&h_rootsegs_, sizeof(Segment) * max_slots, hipHostMallocDefault));
+    ZMC_HIP(hipHostMalloc((void**)&h_bsegs_, sizeof(BSeg) * max_slots, hipHostMallocDefault));
+    ZMC_HIP(hipHostMalloc((void**)&h_stats_, sizeof(SegStats) * max_slots, hipHostMallocDefault));
+    ZMC_HIP(hipHostMalloc((void**)&h_prev_, sizeof(double2) * max_slots, hipHostMallocDefault));
+    ZMC_HIP(hipDeviceGetAttribute(&n_cu_, hipDeviceAttributeMultiprocessorCount, device));
+    ZMC_HIP(hipEventCreate(&ev_sample0_));
+    ZMC_HIP(hipEventCreate(&ev_sample1_));
+    slots_.assign(max_slots, HostSlot());
+    return ZMC_OK;
+}
+
+void Engine::teardown()
+{
+    void* hs[] = {h_slots_, h_segs_, h_segs2_, h_rootsegs_, h_bsegs_, h_stats_, h_prev_};
+    for (void* p : hs)
+        if (p) (void)hipHostFree(p);
+    h_slots_ = nullptr;
+    h_segs_ = h_segs2_ = h_rootsegs_ = nullptr;
+    h_bsegs_ = nullptr;
+    h_stats_ = nullptr;
+    h_prev_ = nullptr;
+    if (ev_sample0_) (void)hipEventDestroy(ev_sample0_);
+    if (ev_sample1_) (void)hipEventDestroy(ev_sample1_);
+    ev_sample0_ = ev_sample1_ = nullptr;
+    slots_.clear();
+    cap_cache_.clear();
+}
+
+int Engine::nch_of(const zmc_request& r) const
+{
+    const int64_t chunk = 4LL * kSampleThreads * tiles_->get(r.integrand, r.dim, r.eval);
+    return (int)ceil_div(r.samples_per_cube, chunk);
+}
+
+int Engine::capacity(int integrand, int dim, int eval)
+{
+    const int key = integrand * 1000 + dim * 2 + eval;
+    auto it = cap_cache_.find(key);
+    if (it != cap_cache_.end()) return it->second;
+    int nb = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sample_kernel_ptr(integrand, dim, eval),
+                                                                kSampleThreads, 0);
+    if (e != hipSuccess || nb < 1) nb = 1;
+    const int cap = nb * std::max(n_cu_, 1);
+    cap_cache_[key] = cap;
+    return cap;
+}
+
+int Engine::fill_slot_desc(int slot, const zmc_request& r, hipStream_t st)
+{
+    SlotDesc& d = h_slots_[slot];
+    memset(&d, 0, sizeof(d));
+    d.integrand = r.integrand;
+    d.dim = r.dim;
+    d.eval = r.eval;
+    d.divisions = r.divisions_per_axis;
+    d.trials = r.trials;
+    d.max_depth = r.max_depth;
+    d.groups = tiles_->get(r.integrand, r.dim, r.eval);
+    d.nch = nch_of(r);
+    d.samples = r.samples_per_cube;
+    d.max_cubes = r.max_cubes_per_level > 0 ? r.max_cubes_per_level : ZMC_DEFAULT_MAX_CUBES;
+    d.sigma_mult = r.sigma_mult;
+    d.rtol = r.rtol;
+    d.seed = r.seed;
+    for (int i = 0; i < r.dim; ++i) {
+        d.lower[i] = r.lower[i];
+        d.h0[i] = (r.upper[i] - r.lower[i]) / (double)r.divisions_per_axis;
+    }
+    for (int j = 0; j < r.n_params && j < ZMC_MAX_PARAMS; ++j) d.params[j] = r.params[j];
+    ZMC_HIP(hipMemcpyAsync(d_slots_ + slot, &d, sizeof(SlotDesc), hipMemcpyHostToDevice, st));
+    return ZMC_OK;
+}
+
+// Bytes one integral can hold at its largest level: current list + work
+// arrays + next list, with the next level bounded by Cantelli's inequality
+// (at most n / (1 + sigma_mult^2) cubes exceed mean + sigma_mult * std) and
+// by the per-level cap.
+size_t Engine::reservation_bytes(const zmc_request& r) const
+{
+    const int64_t cap = r.max_cubes_per_level > 0 ? r.max_cubes_per_level : ZMC_DEFAULT_MAX_CUBES;
+    const int64_t k = (int64_t)ipow_u64((uint64_t)r.divisions_per_axis, r.dim);
+    int64_t n = k, worst = k, worst_next = 0;
+    for (int l = 0; l < r.max_depth; ++l) {
+        const double frac = r.sigma_mult > 0 ? 1.0 / (1.0 + r.sigma_mult * r.sigma_mult) : 1.0;
+        int64_t nsel = (int64_t)floor((double)n * frac);
+        if (r.sigma_mult == 0.0) nsel = n - 1;
+        int64_t nn = nsel << r.dim;
+        if (nn > cap || nn < 0) nn = cap;
+        worst_next = std::max(worst_next, nn);
+        worst = std::max(worst, nn);
+        n = nn;
+        if (n == 0) break;
+    }
+    const int64_t per_cube = 8 + 16LL * r.trials * nch_of(r) + 8 + 8 + 1 + 1;
+    return (size_t)(worst * per_cube + worst_next * 8 + 4 * 4096);
+}
+
+void Engine::record_level(HostSlot& hs, const SegStats& S, int64_t n, double ms, float sample_ms, int launches)
+{
+    zmc_result& R = hs.res;
+    const int l = hs.level;
+    R.sample_ms_per_level[l] = sample_ms;
+    R.sample_launches_per_level[l] = launches;
+    R.levels_run = l + 1;
+    R.cubes_per_level[l] = (uint64_t)n;
+    R.selected_per_level[l] = (uint64_t)S.n_sel;
+    R.thr_per_level[l] = S.thr;
+    R.min_margin_per_level[l] = (S.min_margin >= DBL_MAX) ? INFINITY : S.min_margin;
+    R.ms_per_level[l] = (float)ms;
+    R.n_samples += (uint64_t)n * (uint64_t)hs.req.trials * (uint64_t)hs.req.samples_per_cube;
+    R.n_cubes += (uint64_t)n;
+    hs.totM = S.totM;
+    hs.totS2 = S.totS2;
+    if (S.decision == kTruncated) R.flags |= ZMC_F_TRUNCATED;
+    if (S.decision == kRtolMet) R.flags |= ZMC_F_RTOL_MET;
+    if (S.nonfinite) R.status = ZMC_ENONFINITE;
+}
+
+void Engine::finish(HostSlot& hs)
+{
+    zmc_result& R = hs.res;
+    R.integral = hs.totM;
+    R.std = sqrt(hs.totS2);
+    R.stderr_ = sqrt(hs.totS2 / (double)(hs.req.trials - 1));
+}
+
+static void init_result(zmc_result& R)
+{
+    memset(&R, 0, sizeof(R));
+    for (int l = 0; l < ZMC_MAX_LEVELS; ++l) {
+        R.thr_per_level[l] = NAN;
+        R.min_margin_per_level[l] = NAN;
+    }
+    R.integral = R.std = R.stderr_ = NAN;
+}
+
+// ---------------------------------------------------------------------------
+// One level over the whole current list.
+int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur_uid, int cur_side,
+                 zmc_trace* trace, bool stats_only, bool want_sums)
+{
+    const int ns = (int)live.size();
+    int64_t cube = 0, part = 0, tile = 0;
+    bool any_thr = false;
+    for (int i = 0; i < ns; ++i) {
+        HostSlot& hs = slots_[live[i].slot];
+        const zmc_request& r = hs.req;
+        const int64_t n = live[i].n_cubes;
+        Segment& g = h_segs_[i];
+        memset(&g, 0, sizeof(g));
+        g.slot = live[i].slot;
+        g.level = hs.level;
+        g.cube_base = cube;
+        g.n_cubes = n;
+        g.part_base = part;
+        g.tile_base = tile;
+        g.n_tiles = ceil_div(n, kTileCubes);
+        g.need_thr = (!stats_only && hs.level < r.max_depth) ? 1 : 0;
+        any_thr |= g.need_thr != 0;
+        h_prev_[i] = make_double2(hs.totM, hs.totS2);
+        cube += n;
+        part += n * (int64_t)r.trials * nch_of(r);
+        tile += g.n_tiles;
+    }
+    n_list_ = cube;
+    n_tiles_ = tile;
+    cur_uid_ = cur_uid;
+    double2* partial = (double2*)arena_.alloc(cur_side, (size_t)part * sizeof(double2));
+    cur_m_ = (double*)arena_.alloc(cur_side, (size_t)cube * sizeof(double));
+    cur_s_ = (double*)arena_.alloc(cur_side, (size_t)cube * sizeof(double));
+    cur_sel_ = (uint8_t*)arena_.alloc(cur_side, (size_t)cube);
+    cur_tiles_ = (TileRec*)arena_.alloc(cur_side, (size_t)tile * sizeof(TileRec));
+    cur_S1_ = cur_S2_ = nullptr;
+    // per-(cube, trial) sums are only kept for a single integral (trace,
+    // cube estimates), where every cube has the same number of trials
+    const bool sums = ns == 1 && (want_sums || trace != nullptr);
+    int64_t n_trial_entries = 0;
+    if (sums) {
+        for (int i = 0; i < ns; ++i) n_trial_entries += live[i].n_cubes * slots_[live[i].slot].req.trials;
+        cur_S1_ = (double*)arena_.alloc(cur_side, (size_t)n_trial_entries * sizeof(double));
+        cur_S2_ = (double*)arena_.alloc(cur_side, (size_t)n_trial_entries * sizeof(double));
+    }
+    if (!partial || !cur_m_ || !cur_s_ || !cur_sel_ || !cur_tiles_ || (sums && (!cur_S1_ || !cur_S2_))) {
+        set_error("arena exhausted");
+        return ZMC_ENOMEM;
+    }
+
+    ZMC_HIP(hipMemcpyAsync(d_segs_, h_segs_, ns * sizeof(Segment), hipMemcpyHostToDevice, st));
+    ZMC_HIP(hipMemcpyAsync(d_prev_, h_prev_, ns * sizeof(double2), hipMemcpyHostToDevice, st));
+
+    // sampling: one persistent launch per (integrand, dim, eval) bucket
+    std::map<int, std::vector<int>> buckets;
+    for (int i = 0; i < ns; ++i) {
+        const zmc_request& r = slots_[live[i].slot].req;
+        buckets[r.integrand * 1000 + r.dim * 2 + r.eval].push_back(i);
+    }
+    int nb = 0;
+    struct Launch {
+        int off, count, integrand, dim, eval, groups;
+        int64_t units;
+    };
+    std::vector<Launch> launches;
+    for (auto& kv : buckets) {
+        Launch L;
+        L.off = nb;
+        L.count = (int)kv.second.size();
+        const zmc_request& r0 = slots_[live[kv.second[0]].slot].req;
+        L.integrand = r0.integrand;
+        L.dim = r0.dim;
+        L.eval = r0.eval;
+        L.groups = tiles_->get(r0.integrand, r0.dim, r0.eval);
+        int64_t u = 0;
+        for (int i : kv.second) {
+            const zmc_request& r = slots_[live[i].slot].req;
+            h_bsegs_[nb].unit_base = u;
+            h_bsegs_[nb].seg = i;
+            h_bsegs_[nb].pad = 0;
+            ++nb;
+            u += live[i].n_cubes * (int64_t)r.trials * nch_of(r);
+        }
+        L.units = u;
+        launches.push_back(L);
+    }
+    ZMC_HIP(hipMemcpyAsync(d_bsegs_, h_bsegs_, nb * sizeof(BSeg), hipMemcpyHostToDevice, st));
+    ZMC_HIP(hipEventRecord(ev_sample0_, st));
+    int n_launch = 0;
+    for (const Launch& L : launches) {
+        if (L.units <= 0) continue;
+        SampleArgs a;
+        a.slots = d_slots_;
+        a.segs = d_segs_;
+        a.bsegs = d_bsegs_ + L.off;
+        a.n_bsegs = L.count;
+        a.groups = L.groups;
+        a.total_units = L.units;
+        a.uid = cur_uid;
+        a.partial = partial;
+        const int64_t cap = capacity(L.integrand, L.dim, L.eval);
+        const int grid = (int)std::min<int64_t>(L.units, cap);
+        ZMC_HIP(launch_sample(L.integrand, L.dim, L.eval, grid, st, a));
+        ++n_launch;
+    }
+    ZMC_HIP(hipEventRecord(ev_sample1_, st));
+
+    LevelArgs la;
+    memset(&la, 0, sizeof(la));
+    la.slots = d_slots_;
+    la.segs = d_segs_;
+    la.n_segs = ns;
+    la.n_tiles = tile;
+    la.uid = cur_uid;
+    la.partial = partial;
+    la.m = cur_m_;
+    la.s = cur_s_;
+    la.sel = cur_sel_;
+    la.tiles = cur_tiles_;
+    la.stats = d_stats_;
+    la.prev_tot = d_prev_;
+    la.tr_S1 = cur_S1_;
+    la.tr_S2 = cur_S2_;
+    ZMC_HIP(launch_finalize(la, st));
+    if (!stats_only) {
+        if (any_thr) ZMC_HIP(launch_threshold(la, st));
+        ZMC_HIP(launch_select(la, st));
+        ZMC_HIP(hipMemcpyAsync(h_stats_, d_stats_, ns * sizeof(SegStats), hipMemcpyDeviceToHost, st));
+    }
+    if (trace && ns == 1) {
+        const HostSlot& hs = slots_[live[0].slot];
+        const int l = hs.level;
+        if (l < trace->max_levels && l < ZMC_MAX_LEVELS) {
+            trace->n[l] = cube;
+            const int64_t c = std::min<int64_t>(cube, trace->capacity);
+            const int n1 = hs.req.trials;
+            if (c > 0) {
+                if (trace->uid[l]) ZMC_HIP(hipMemcpyAsync(trace->uid[l], cur_uid, c * 8, hipMemcpyDeviceToHost, st));
+                if (trace->m[l]) ZMC_HIP(hipMemcpyAsync(trace->m[l], cur_m_, c * 8, hipMemcpyDeviceToHost, st));
+                if (trace->s[l]) ZMC_HIP(hipMemcpyAsync(trace->s[l], cur_s_, c * 8, hipMemcpyDeviceToHost, st));
+                if (trace->sel[l]) ZMC_HIP(hipMemcpyAsync(trace->sel[l], cur_sel_, c, hipMemcpyDeviceToHost, st));
+                if (trace->S1[l])
+                    ZMC_HIP(hipMemcpyAsync(trace->S1[l], cur_S1_, c * n1 * 8, hipMemcpyDeviceToHost, st));
+                if (trace->S2[l])
+                    ZMC_HIP(hipMemcpyAsync(trace->S2[l], cur_S2_, c * n1 * 8, hipMemcpyDeviceToHost, st));
+            }
+        }
+    }
+    ZMC_HIP(hipStreamSynchronize(st));
+    ZMC_HIP(hipGetLastError());
+    last_sample_launches_ = n_launch;
+    last_sample_ms_ = 0.0f;
+    ZMC_HIP(hipEventElapsedTime(&last_sample_ms_, ev_sample0_, ev_sample1_));
+    return ZMC_OK;
+}
+
+// Lay out the next list: children of every continuing segment (in list
+// order), then the roots of newly admitted integrals; launch spawn and roots.
+int Engine::next_list(hipStream_t st, std::vector<LiveSeg>& live, const std::vector<int>& split,
+                      const std::vector<LiveSeg>& fresh, uint64_t*& cur_uid, int& cur_side)
+{
+    std::vector<LiveSeg> nxt;
+    int64_t total = 0;
+    const int ns = (int)live.size();
+    bool any_split = false;
+    for (int i = 0; i < ns; ++i) {
+        h_segs2_[i] = h_segs_[i];
+        h_segs2_[i].do_split = 0;
+        h_segs2_[i].child_base = 0;
+        if (split[i]) {
+            HostSlot& hs = slots_[live[i].slot];
+            const int64_t nc = h_stats_[i].n_sel << hs.req.dim;
+            h_segs2_[i].do_split = 1;
+            h_segs2_[i].child_base = total;
+            total += nc;
+            nxt.push_back({live[i].slot, nc});
+            any_split = true;
+        }
+    }
+    const int64_t root_base = total;
+    for (size_t j = 0; j < fresh.size(); ++j) {
+        Segment& g = h_rootsegs_[j];
+        memset(&g, 0, sizeof(g));
+        g.slot = fresh[j].slot;
+        g.cube_base = total;
+        g.n_cubes = fresh[j].n_cubes;
+        total += fresh[j].n_cubes;
+        nxt.push_back(fresh[j]);
+    }
+    (void)root_base;
+    const int other = cur_side ^ 1;
+    uint64_t* next_uid = nullptr;
+    if (total > 0) {
+        next_uid = (uint64_t*)arena_.alloc(other, (size_t)total * sizeof(uint64_t));
+        if (!next_uid) {
+            set_error("arena exhausted (next level list)");
+            return ZMC_ENOMEM;
+        }
+    }
+    if (any_split) {
+        ZMC_HIP(hipMemcpyAsync(d_segs_, h_segs2_, ns * sizeof(Segment), hipMemcpyHostToDevice, st));
+        LevelArgs la;
+        memset(&la, 0, sizeof(la));
+        la.slots = d_slots_;
+        la.segs = d_segs_;
+        la.n_segs = ns;
+        la.n_tiles = n_tiles_;
+        la.uid = cur_uid;
+        la.sel = cur_sel_;
+        la.tiles = cur_tiles_;
+        la.next_uid = next_uid;
+        ZMC_HIP(launch_spawn(la, st));
+    }
+    if (!fresh.empty()) {
+        ZMC_HIP(hipMemcpyAsync(d_rootsegs_, h_rootsegs_, fresh.size() * sizeof(Segment), hipMemcpyHostToDevice,
+                               st));
+        RootArgs ra;
+        ra.segs = d_rootsegs_;
+        ra.n_segs = (int)fresh.size();
+        int64_t mx = 1;
+        for (auto& f : fresh) mx = std::max(mx, f.n_cubes);
+        ra.blocks_per_seg = (int)std::min<int64_t>(64, ceil_div(mx, 4096));
+        ra.uid = next_uid;
+        ZMC_HIP(launch_roots(ra, st));
+    }
+    // levels advance for the split segments
+    for (int i = 0; i < ns; ++i)
+        if (split[i]) slots_[live[i].slot].level += 1;
+    for (auto& f : fresh) slots_[f.slot].level = 0;
+    arena_.reset(cur_side);
+    cur_side = other;
+    cur_uid = next_uid;
+    live.swap(nxt);
+    return ZMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Shared level loop of run() and serving.
+int Engine::drive(hipStream_t st, Admission& adm, zmc_trace* trace, const volatile bool* stop_flag,
+                  uint64_t* levels_stepped)
+{
+    std::vector<int> free_ids;
+    for (int i = max_slots_ - 1; i >= 0; --i) free_ids.push_back(i);
+    std::vector<LiveSeg> live;
+    uint64_t* cur_uid = nullptr;
+    int cur_side = 0;
+    arena_.reset(0);
+    arena_.reset(1);
+    size_t reserved = 0;
+    bool more = true;
+    int rc_all = ZMC_OK;
+
+    while (true) {
+        std::vector<int> split(live.size(), 0);
+        if (!live.empty()) {
+            const double t0 = now_ms();
+            int rc = step(st, live, cur_uid, cur_side, trace, false, false);
+            const double ms = now_ms() - t0;
+            if (levels_stepped) ++*levels_stepped;
+            for (size_t i = 0; i < live.size(); ++i) {
+                HostSlot& hs = slots_[live[i].slot];
+                bool done = true;
+                if (rc != ZMC_OK) {
+                    hs.res.status = rc;
+                } else {
+                    const SegStats& S = h_stats_[i];
+                    record_level(hs, S, live[i].n_cubes, ms, last_sample_ms_, last_sample_launches_);
+                    if (hs.res.status == ZMC_OK && S.decision == kSplit) done = false;
+                    if (adm.cancelled && adm.cancelled(hs.ticket)) {
+                        hs.res.status = ZMC_ECANCELED;
+                        done = true;
+                    }
+                }
+                if (done) {
+                    finish(hs);
+                    adm.retire(hs);
+                    reserved -= std::min(reserved, hs.reserve);
+                    free_ids.push_back(live[i].slot);
+                } else {
+                    split[i] = 1;
+                }
+            }
+            if (rc != ZMC_OK) {
+                rc_all = rc;
+                live.clear();
+                split.clear();
+                cur_uid = nullptr;
+                arena_.reset(0);
+                arena_.reset(1);
+                if (rc == ZMC_EDEVICE) return rc;
+            }
+        }
+        if (stop_flag && *stop_flag) {
+            // retire what is still resident
+            for (size_t i = 0; i < live.size(); ++i)
+                if (split[i]) {
+                    HostSlot& hs = slots_[live[i].slot];
+                    hs.res.status = ZMC_ECANCELED;
+                    finish(hs);
+                    adm.retire(hs);
+                }
+            return rc_all;
+        }
+        // admission at the level boundary
+        std::vector<HostSlot> incoming;
+        bool idle = true;
+        for (int v : split) idle &= (v == 0);
+        if (more) {
+            const size_t budget = arena_.size() > reserved ? arena_.size() - reserved : 0;
+            more = adm.admit(incoming, (int)free_ids.size(), budget, idle);
+        }
+        std::vector<LiveSeg> fresh;
+        for (HostSlot& in : incoming) {
+            const int id = free_ids.back();
+            free_ids.pop_back();
+            slots_[id] = in;
+            HostSlot& hs = slots_[id];
+            hs.level = 0;
+            hs.totM = hs.totS2 = 0.0;
+            reserved += hs.reserve;
+            int rc = fill_slot_desc(id, hs.req, st);
+            if (rc != ZMC_OK) return rc;
+            fresh.push_back({id, (int64_t)ipow_u64((uint64_t)hs.req.divisions_per_axis, hs.req.dim)});
+        }
+        if (idle && fresh.empty()) {
+            if (!more) break;
+            live.clear();
+            continue;
+        }
+        int rc = next_list(st, live, split, fresh, cur_uid, cur_side);
+        if (rc == ZMC_ENOMEM) {
+            // the next level does not fit: every affected integral fails
+            rc_all = rc;
+            for (size_t i = 0; i < live.size(); ++i)
+                if (i < split.size() && split[i]) {
+                    HostSlot& hs = slots_[live[i].slot];
+                    hs.res.status = ZMC_ENOMEM;
+                    finish(hs);
+                    adm.retire(hs);
+                    reserved -= std::min(reserved, hs.reserve);
+                    free_ids.push_back(live[i].slot);
+                }
+            for (auto& f : fresh) {
+                HostSlot& hs = slots_[f.slot];
+                hs.res.status = ZMC_ENOMEM;
+                finish(hs);
+                adm.retire(hs);
+                reserved -= std::min(reserved, hs.reserve);
+                free_ids.push_back(f.slot);
+            }
+            live.clear();
+            cur_uid = nullptr;
+            arena_.reset(0);
+            arena_.reset(1);
+            continue;
+        }
+        if (rc != ZMC_OK) return rc;
+    }
+    return rc_all;
+}
+
+int Engine::run(const zmc_request* reqs, int n, hipStream_t st, zmc_result* outs, zmc_trace* trace)
+{
+    if (n > max_slots_) {
+        set_error("more requests than slots");
+        return ZMC_EINVAL;
+    }
+    std::vector<int> id_of_slot(max_slots_, -1);
+    int given = 0;
+    Admission adm;
+    adm.admit = [&](std::vector<HostSlot>& out, int free_slots, size_t, bool) {
+        if (given == 0) {
+            for (int i = 0; i < n && i < free_slots; ++i) {
+                HostSlot hs;
+                hs.req = reqs[i];
+                init_result(hs.res);
+                hs.ticket = (uint64_t)i;
+                out.push_back(hs);
+            }
+            given = n;
+        }
+        return false;
+    };
+    adm.retire = [&](HostSlot& hs) {
+        outs[hs.ticket] = hs.res;
+    };
+    adm.cancelled = nullptr;
+    const double t0 = now_ms();
+    int rc = drive(st, adm, n == 1 ? trace : nullptr, nullptr, nullptr);
+    const double t1 = now_ms();
+    for (int i = 0; i < n; ++i) outs[i].latency_ms = t1 - t0;
+    return rc;
+}
+
+int Engine::cube_estimates(const zmc_request& req, int level, const uint64_t* uids, int64_t n, double* m,
+                           double* s, double* S1, double* S2, hipStream_t st)
+{
+    if (n <= 0) return ZMC_OK;
+    arena_.reset(0);
+    arena_.reset(1);
+    HostSlot& hs = slots_[0];
+    hs = HostSlot();
+    hs.req = req;
+    init_result(hs.res);
+    hs.level = level;
+    int rc = fill_slot_desc(0, req, st);
+    if (rc != ZMC_OK) return rc;
+    uint64_t* d_uid = (uint64_t*)arena_.alloc(1, (size_t)n * 8);
+    if (!d_uid) return ZMC_ENOMEM;
+    ZMC_HIP(hipMemcpyAsync(d_uid, uids, (size_t)n * 8, hipMemcpyHostToDevice, st));
+    std::vector<LiveSeg> live{{0, n}};
+    rc = step(st, live, d_uid, 0, nullptr, true, S1 != nullptr || S2 != nullptr);
+    if (rc != ZMC_OK) return rc;
+    const int n1 = req.trials;
+    if (m) ZMC_HIP(hipMemcpyAsync(m, cur_m_, n * 8, hipMemcpyDeviceToHost, st));
+    if (s) ZMC_HIP(hipMemcpyAsync(s, cur_s_, n * 8, hipMemcpyDeviceToHost, st));
+    if (S1) ZMC_HIP(hipMemcpyAsync(S1, cur_S1_, n * n1 * 8, hipMemcpyDeviceToHost, st));
+    if (S2) ZMC_HIP(hipMemcpyAsync(S2, cur_S2_, n * n1 * 8, hipMemcpyDeviceToHost, st));
+    ZMC_HIP(hipStreamSynchronize(st));
+    arena_.reset(0);
+    arena_.reset(1);
+    return ZMC_OK;
+}
+
+int Engine::debug_philox(uint32_t k0, uint32_t k1, const uint32_t* ctr, int64_t n, uint32_t* out, hipStream_t st)
+{
+    arena_.reset(0);
+    uint32_t* dc = (uint32_t*)arena_.alloc(0, (size_t)n * 16);
+    uint32_t* dout = (uint32_t*)arena_.alloc(0, (size_t)n * 16);
+    if (!dc || !dout) return ZMC_ENOMEM;
+    ZMC_HIP(hipMemcpyAsync(dc, ctr, (size_t)n * 16, hipMemcpyHostToDevice, st));
+    ZMC_HIP(launch_debug_philox(k0, k1, dc, dout, n, st));
+    ZMC_HIP(hipMemcpyAsync(out, dout, (size_t)n * 16, hipMemcpyDeviceToHost, st));
+    ZMC_HIP(hipStreamSynchronize(st));
+    arena_.reset(0);
+    return ZMC_OK;
+}
+
+int Engine::debug_points(const zmc_request& req, int level, uint64_t uid, int trial, int64_t s0, int64_t n,
+                         double* x, hipStream_t st)
+{
+    arena_.reset(0);
+    int rc = fill_slot_desc(0, req, st);
+    if (rc != ZMC_OK) return rc;
+    double* dx = (double*)arena_.alloc(0, (size_t)n * req.dim * 8);
+    if (!dx) return ZMC_ENOMEM;
+    ZMC_HIP(launch_debug_points(d_slots_, level, uid, trial, s0, n, dx, st));
+    ZMC_HIP(hipMemcpyAsync(x, dx, (size_t)n * req.dim * 8, hipMemcpyDeviceToHost, st));
+    ZMC_HIP(hipStreamSynchronize(st));
+    arena_.reset(0);
+    return ZMC_OK;
+}
+
+} // namespace zmc

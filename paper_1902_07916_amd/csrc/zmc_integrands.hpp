@@ -1,0 +1,380 @@
+// zmc_integrands.hpp -- the integrand registry on the device, in two forms:
+//
+//  * FP64: f(x) from the absolute point x, the plain definition;
+//  * FP32: f from the per-dimension cell values v_i in [1, 2) (see
+//    unit_interval_f32) and per-cube constants formed once in FP64, so that
+//    every FP32 quantity is cube-relative (an offset from the cube corner, a
+//    phase reduced modulo one revolution).  Absolute coordinates such as
+//    x ~ 10 never enter FP32 arithmetic.
+//
+// With u = v - (1 - 2^-24) and x_i = lo_i + h_i u_i, every coordinate is
+// x_i = b_i + h_i v_i with b_i = lo_i - h_i (1 - 2^-24).
+//
+// The paper's test functions are f1 = sin(sum x_i) and the 9-D Gaussian f2
+// (Sec. 3); the Genz families are the batched/serving workloads' integrands.
+#pragma once
+
+#include "zmc_device.hpp"
+
+namespace zmc {
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+constexpr double kInvTwoPi = 0.15915494309189533576888376337251;
+constexpr double kLog2e = 1.4426950408889634073599246810019;
+constexpr double kOneMinus = 1.0 - 0x1p-24;
+
+// sin(2 pi r): r is reduced to t in [-1/4, 1/4] by the exact steps
+// t = r - rint(r) and t = (+-1/2) - t, which keep the result odd-symmetric
+// (so its error has no mean over a period), then the Taylor series of
+// sin(2 pi t) through t^13 (truncation < 7e-10) is summed by Horner in t^2.
+// Coefficients: (-1)^k (2 pi)^(2k+1) / (2k+1)!.
+__device__ __forceinline__ float sin_rev(float r)
+{
+    float t = r - __builtin_rintf(r);
+    const float half = __builtin_copysignf(0.5f, t);
+    t = (__builtin_fabsf(t) > 0.25f) ? half - t : t;
+    const float t2 = t * t;
+    float p = 3.8199524879455566f;
+    p = __builtin_fmaf(p, t2, -15.094642639160156f);
+    p = __builtin_fmaf(p, t2, 42.058692932128906f);
+    p = __builtin_fmaf(p, t2, -76.70585632324219f);
+    p = __builtin_fmaf(p, t2, 81.6052474975586f);
+    p = __builtin_fmaf(p, t2, -41.34170150756836f);
+    p = __builtin_fmaf(p, t2, 6.2831854820251465f);
+    return p * t;
+}
+
+// frac(x) in FP64 for the per-cube phase offsets.
+__device__ __forceinline__ double frac64(double x) { return x - floor(x); }
+
+// Integer power by squaring (exponent known per launch, small).
+template <typename T>
+__device__ __forceinline__ T ipow(T x, int n)
+{
+    T r = (T)1;
+    while (n > 0) {
+        if (n & 1) r *= x;
+        x *= x;
+        n >>= 1;
+    }
+    return r;
+}
+
+template <int F, int D>
+struct Integrand;
+
+// ---- ZMC_GAUSS: A exp(-sum (x_i - mu_i)^2 / (2 sigma^2)) -------------------
+template <int D>
+struct Integrand<ZMC_GAUSS, D> {
+    struct P64 {
+        double mu[D], k, A;
+    };
+    struct P32 {
+        float a[D], m[D], k2, A;
+    };
+    __device__ static void prep64(const SlotDesc& sd, P64& p)
+    {
+        const double s = sd.params[0];
+        p.A = sd.params[1];
+        p.k = -1.0 / (2.0 * s * s);
+        for (int i = 0; i < D; ++i) p.mu[i] = sd.params[2 + i];
+    }
+    __device__ static double f64(const P64& p, const double* x)
+    {
+        double q = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const double d = x[i] - p.mu[i];
+            q = fma(d, d, q);
+        }
+        return p.A * exp(q * p.k);
+    }
+    __device__ static void prep32(const SlotDesc& sd, const double* lo, const double* h, P32& p)
+    {
+        const double s = sd.params[0];
+        p.A = (float)sd.params[1];
+        p.k2 = (float)(-kLog2e / (2.0 * s * s));
+        for (int i = 0; i < D; ++i) {
+            p.a[i] = (float)(lo[i] - h[i] * kOneMinus - sd.params[2 + i]);
+            p.m[i] = (float)h[i];
+        }
+    }
+    __device__ static float f32(const P32& p, const float* v)
+    {
+        float q = 0.0f;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const float t = __builtin_fmaf(p.m[i], v[i], p.a[i]);
+            q = __builtin_fmaf(t, t, q);
+        }
+        return p.A * __builtin_amdgcn_exp2f(q * p.k2);
+    }
+};
+
+// ---- ZMC_SIN_SUM: sin(sum x_i) ---------------------------------------------
+template <int D>
+struct Integrand<ZMC_SIN_SUM, D> {
+    struct P64 {
+        int dummy;
+    };
+    struct P32 {
+        float m[D], r0;
+    };
+    __device__ static void prep64(const SlotDesc&, P64&) {}
+    __device__ static double f64(const P64&, const double* x)
+    {
+        double t = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) t += x[i];
+        return sin(t);
+    }
+    __device__ static void prep32(const SlotDesc&, const double* lo, const double* h, P32& p)
+    {
+        double b = 0.0;
+        for (int i = 0; i < D; ++i) {
+            b += lo[i] - h[i] * kOneMinus;
+            p.m[i] = (float)(h[i] * kInvTwoPi);
+        }
+        p.r0 = (float)frac64(b * kInvTwoPi);
+    }
+    __device__ static float f32(const P32& p, const float* v)
+    {
+        float r = p.r0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) r = __builtin_fmaf(p.m[i], v[i], r);
+        return sin_rev(r);
+    }
+};
+
+// ---- ZMC_GENZ_OSC: cos(2 pi u + sum c_i x_i) = sin(2 pi (u + 1/4 + sum c_i x_i / 2pi))
+template <int D>
+struct Integrand<ZMC_GENZ_OSC, D> {
+    struct P64 {
+        double c[D], ph;
+    };
+    struct P32 {
+        float m[D], r0;
+    };
+    __device__ static void prep64(const SlotDesc& sd, P64& p)
+    {
+        p.ph = kTwoPi * sd.params[0];
+        for (int i = 0; i < D; ++i) p.c[i] = sd.params[1 + i];
+    }
+    __device__ static double f64(const P64& p, const double* x)
+    {
+        double t = p.ph;
+#pragma unroll
+        for (int i = 0; i < D; ++i) t = fma(p.c[i], x[i], t);
+        return cos(t);
+    }
+    __device__ static void prep32(const SlotDesc& sd, const double* lo, const double* h, P32& p)
+    {
+        double b = sd.params[0] + 0.25; // revolutions
+        for (int i = 0; i < D; ++i) {
+            const double c = sd.params[1 + i];
+            b += c * (lo[i] - h[i] * kOneMinus) * kInvTwoPi;
+            p.m[i] = (float)(c * h[i] * kInvTwoPi);
+        }
+        p.r0 = (float)frac64(b);
+    }
+    __device__ static float f32(const P32& p, const float* v)
+    {
+        float r = p.r0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) r = __builtin_fmaf(p.m[i], v[i], r);
+        return sin_rev(r);
+    }
+};
+
+// ---- ZMC_GENZ_PPEAK: prod 1 / (c_i^-2 + (x_i - w_i)^2) ----------------------
+template <int D>
+struct Integrand<ZMC_GENZ_PPEAK, D> {
+    struct P64 {
+        double e[D], w[D];
+    };
+    struct P32 {
+        float a[D], m[D], e[D];
+    };
+    __device__ static void prep64(const SlotDesc& sd, P64& p)
+    {
+        for (int i = 0; i < D; ++i) {
+            const double c = sd.params[i];
+            p.e[i] = 1.0 / (c * c);
+            p.w[i] = sd.params[D + i];
+        }
+    }
+    __device__ static double f64(const P64& p, const double* x)
+    {
+        double den = 1.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const double d = x[i] - p.w[i];
+            den *= fma(d, d, p.e[i]);
+        }
+        return 1.0 / den;
+    }
+    __device__ static void prep32(const SlotDesc& sd, const double* lo, const double* h, P32& p)
+    {
+        for (int i = 0; i < D; ++i) {
+            const double c = sd.params[i];
+            p.e[i] = (float)(1.0 / (c * c));
+            p.a[i] = (float)(lo[i] - h[i] * kOneMinus - sd.params[D + i]);
+            p.m[i] = (float)h[i];
+        }
+    }
+    __device__ static float f32(const P32& p, const float* v)
+    {
+        float den = 1.0f;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const float t = __builtin_fmaf(p.m[i], v[i], p.a[i]);
+            den *= __builtin_fmaf(t, t, p.e[i]);
+        }
+        return __builtin_amdgcn_rcpf(den);
+    }
+};
+
+// ---- ZMC_GENZ_CPEAK: (1 + sum c_i x_i)^-(D+1) -------------------------------
+template <int D>
+struct Integrand<ZMC_GENZ_CPEAK, D> {
+    struct P64 {
+        double c[D];
+    };
+    struct P32 {
+        float m[D], b0;
+    };
+    __device__ static void prep64(const SlotDesc& sd, P64& p)
+    {
+        for (int i = 0; i < D; ++i) p.c[i] = sd.params[i];
+    }
+    __device__ static double f64(const P64& p, const double* x)
+    {
+        double t = 1.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) t = fma(p.c[i], x[i], t);
+        return 1.0 / ipow(t, D + 1);
+    }
+    __device__ static void prep32(const SlotDesc& sd, const double* lo, const double* h, P32& p)
+    {
+        double b = 1.0;
+        for (int i = 0; i < D; ++i) {
+            const double c = sd.params[i];
+            b += c * (lo[i] - h[i] * kOneMinus);
+            p.m[i] = (float)(c * h[i]);
+        }
+        p.b0 = (float)b;
+    }
+    __device__ static float f32(const P32& p, const float* v)
+    {
+        float t = p.b0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) t = __builtin_fmaf(p.m[i], v[i], t);
+        return __builtin_amdgcn_rcpf(ipow(t, D + 1));
+    }
+};
+
+// ---- ZMC_GENZ_GAUSS: exp(-sum c_i^2 (x_i - w_i)^2) --------------------------
+template <int D>
+struct Integrand<ZMC_GENZ_GAUSS, D> {
+    struct P64 {
+        double c[D], w[D];
+    };
+    struct P32 {
+        float a[D], m[D];
+    };
+    __device__ static void prep64(const SlotDesc& sd, P64& p)
+    {
+        for (int i = 0; i < D; ++i) {
+            p.c[i] = sd.params[i];
+            p.w[i] = sd.params[D + i];
+        }
+    }
+    __device__ static double f64(const P64& p, const double* x)
+    {
+        double q = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const double t = p.c[i] * (x[i] - p.w[i]);
+            q = fma(t, t, q);
+        }
+        return exp(-q);
+    }
+    __device__ static void prep32(const SlotDesc& sd, const double* lo, const double* h, P32& p)
+    {
+        // exp(-q) = exp2(-q log2 e): fold sqrt(log2 e) into the offsets
+        const double s = sqrt(kLog2e);
+        for (int i = 0; i < D; ++i) {
+            const double c = sd.params[i] * s;
+            p.a[i] = (float)(c * (lo[i] - h[i] * kOneMinus - sd.params[D + i]));
+            p.m[i] = (float)(c * h[i]);
+        }
+    }
+    __device__ static float f32(const P32& p, const float* v)
+    {
+        float q = 0.0f;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const float t = __builtin_fmaf(p.m[i], v[i], p.a[i]);
+            q = __builtin_fmaf(t, t, q);
+        }
+        return __builtin_amdgcn_exp2f(-q);
+    }
+};
+
+// ---- ZMC_CONST: A -------------------------------------------------------------
+template <int D>
+struct Integrand<ZMC_CONST, D> {
+    struct P64 {
+        double A;
+    };
+    struct P32 {
+        float A;
+    };
+    __device__ static void prep64(const SlotDesc& sd, P64& p) { p.A = sd.params[0]; }
+    __device__ static double f64(const P64& p, const double*) { return p.A; }
+    __device__ static void prep32(const SlotDesc& sd, const double*, const double*, P32& p)
+    {
+        p.A = (float)sd.params[0];
+    }
+    __device__ static float f32(const P32& p, const float*) { return p.A; }
+};
+
+// ---- ZMC_MONOMIAL: prod x_i^p_i -----------------------------------------------
+template <int D>
+struct Integrand<ZMC_MONOMIAL, D> {
+    struct P64 {
+        int e[D];
+    };
+    struct P32 {
+        float b[D], m[D];
+        int e[D];
+    };
+    __device__ static void prep64(const SlotDesc& sd, P64& p)
+    {
+        for (int i = 0; i < D; ++i) p.e[i] = (int)sd.params[i];
+    }
+    __device__ static double f64(const P64& p, const double* x)
+    {
+        double f = 1.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) f *= ipow(x[i], p.e[i]);
+        return f;
+    }
+    __device__ static void prep32(const SlotDesc& sd, const double* lo, const double* h, P32& p)
+    {
+        for (int i = 0; i < D; ++i) {
+            p.e[i] = (int)sd.params[i];
+            p.b[i] = (float)(lo[i] - h[i] * kOneMinus);
+            p.m[i] = (float)h[i];
+        }
+    }
+    __device__ static float f32(const P32& p, const float* v)
+    {
+        float f = 1.0f;
+#pragma unroll
+        for (int i = 0; i < D; ++i) f *= ipow(__builtin_fmaf(p.m[i], v[i], p.b[i]), p.e[i]);
+        return f;
+    }
+};
+
+} // namespace zmc

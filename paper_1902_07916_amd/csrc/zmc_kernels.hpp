@@ -1,0 +1,89 @@
+// zmc_kernels.hpp -- argument blocks and host-side launchers of the device
+// pipeline that runs one level of the tree search over every resident
+// integral:
+//
+//   sample      (cube, trial, chunk) units -> FP64 partial sums S1 = sum f,
+//               S2 = sum f^2 over the chunk's points (one kernel per
+//               (integrand, D, eval) bucket, persistent over its units)
+//   finalize    per cube: I_t = V * S1_t / N, m = mean_t I_t, s = std_t I_t
+//   seg_mean / tile_sqdev / seg_thr
+//               per integral: thr = mean(s) + sigma_mult * std(s)
+//   tile_select per cube: split = s > thr; accepted / selected sums per tile
+//   seg_decide  per integral: totals, stop rules, rank base of every tile
+//   spawn       2^D children of every split cube, in list order
+//   roots       level-0 list of a newly admitted integral
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "zmc_device.hpp"
+
+namespace zmc {
+
+constexpr int kSampleThreads = 256;
+
+struct SampleArgs {
+    const SlotDesc* slots;
+    const Segment* segs;
+    const BSeg* bsegs;
+    int32_t n_bsegs;
+    int32_t groups; // 4-sample groups per thread per chunk
+    int64_t total_units;
+    const uint64_t* uid;
+    double2* partial;
+};
+
+struct LevelArgs {
+    const SlotDesc* slots;
+    const Segment* segs;
+    int32_t n_segs;
+    int32_t pad;
+    int64_t n_tiles;
+    const uint64_t* uid;
+    const double2* partial;
+    double* m;
+    double* s;
+    uint8_t* sel;
+    TileRec* tiles;
+    SegStats* stats;
+    const double2* prev_tot; // per segment: running (M, S2) before this level
+    double* tr_S1;           // optional per (cube, trial) sums (trace)
+    double* tr_S2;
+    uint64_t* next_uid;      // spawn output
+};
+
+struct RootArgs {
+    const Segment* segs; // segments whose roots are written (cube_base, n_cubes)
+    int32_t n_segs;
+    int32_t blocks_per_seg;
+    uint64_t* uid;
+};
+
+// Launchers; each returns the hipError_t of its launch.
+hipError_t launch_sample(int integrand, int dim, int eval, int grid, hipStream_t st, const SampleArgs& a);
+const void* sample_kernel_ptr(int integrand, int dim, int eval);
+hipError_t launch_finalize(const LevelArgs& a, hipStream_t st);
+hipError_t launch_threshold(const LevelArgs& a, hipStream_t st);
+hipError_t launch_select(const LevelArgs& a, hipStream_t st);
+hipError_t launch_spawn(const LevelArgs& a, hipStream_t st);
+hipError_t launch_roots(const RootArgs& a, hipStream_t st);
+hipError_t launch_debug_philox(uint32_t k0, uint32_t k1, const uint32_t* ctr, uint32_t* out, int64_t n,
+                               hipStream_t st);
+hipError_t launch_debug_points(const SlotDesc* sd, int level, uint64_t uid, int trial, int64_t s0, int64_t n,
+                               double* x, hipStream_t st);
+
+// Per-integrand launch tables (one translation unit per integrand).
+#define ZMC_DECLARE_SAMPLE(F)                                                                              \
+    hipError_t launch_sample_##F(int dim, int eval, int grid, hipStream_t st, const SampleArgs& a);        \
+    const void* sample_kernel_ptr_##F(int dim, int eval);
+ZMC_DECLARE_SAMPLE(0)
+ZMC_DECLARE_SAMPLE(1)
+ZMC_DECLARE_SAMPLE(2)
+ZMC_DECLARE_SAMPLE(3)
+ZMC_DECLARE_SAMPLE(4)
+ZMC_DECLARE_SAMPLE(5)
+ZMC_DECLARE_SAMPLE(6)
+ZMC_DECLARE_SAMPLE(7)
+#undef ZMC_DECLARE_SAMPLE
+
+} // namespace zmc

@@ -1,0 +1,519 @@
+// zmc_level.hip -- per-cube and per-integral kernels of one tree level
+// (ZMCintegral, Sec. 2.1): trial mean / standard deviation per sub-domain,
+// the threshold from the mean and standard deviation of the level's standard
+// deviations, selection, acceptance, and the split of the selected cubes.
+//
+// All of these are HBM-bound and small next to the sampling kernel.  The
+// per-cube kernels work on tiles of 1024 consecutive cubes of one segment
+// (256 threads, 4 cubes each, strided so that loads coalesce); per-integral
+// kernels run one 256-thread block per segment over that segment's tiles.
+// Every reduction has a fixed shape (thread-serial over its elements, then
+// wave64 butterflies, then the 4 waves in order), so results are bitwise
+// reproducible and independent of what else is resident.
+#include <float.h>
+
+#include "zmc_kernels.hpp"
+
+namespace zmc {
+
+namespace {
+
+constexpr int kWaves = kLevelThreads / 64;
+constexpr int kPerThread = kTileCubes / kLevelThreads;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_min(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ __forceinline__ int64_t wave_sum_i(int64_t v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Block-wide sum in a fixed order; every thread gets the result.
+__device__ double block_sum(double v, double* sh)
+{
+    v = wave_sum(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = sh[0];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) t += sh[w];
+    return t;
+}
+
+__device__ double block_min(double v, double* sh)
+{
+    v = wave_min(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = sh[0];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) t = fmin(t, sh[w]);
+    return t;
+}
+
+__device__ int64_t block_sum_i(int64_t v, int64_t* sh)
+{
+    v = wave_sum_i(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int64_t t = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) t += sh[w];
+    return t;
+}
+
+// Exclusive prefix of a 0/1 flag over the block in thread order; *total gets
+// the block's count.
+__device__ int block_excl_scan_flag(int flag, int* sh, int* total)
+{
+    const unsigned long long mask = __ballot(flag);
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int in_wave = __popcll(mask & ((1ull << lane) - 1ull));
+    __syncthreads();
+    if (lane == 0) sh[wv] = __popcll(mask);
+    __syncthreads();
+    int base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) {
+        if (w < wv) base += sh[w];
+        tot += sh[w];
+    }
+    *total = tot;
+    return base + in_wave;
+}
+
+// Segment that owns tile t (segments are in list order, tile_base ascending).
+__device__ __forceinline__ int seg_of_tile(const Segment* segs, int n, int64_t t)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].tile_base <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// ---- finalize: per cube I_t = V * S1_t / N, m = mean I_t, s = std I_t ------
+__global__ __launch_bounds__(kLevelThreads) void finalize_kernel(const LevelArgs a)
+{
+    __shared__ double sh[kWaves];
+    const int64_t tile = blockIdx.x;
+    const int si = seg_of_tile(a.segs, a.n_segs, tile);
+    const Segment& sg = a.segs[si];
+    const SlotDesc& sd = a.slots[sg.slot];
+    const int D = sd.dim, n1 = sd.trials, nch = sd.nch;
+    const double V = cube_volume(sd, D, sg.level);
+    const double N = (double)sd.samples;
+    const int64_t first = (tile - sg.tile_base) * kTileCubes;
+    double sum_s = 0.0;
+    int bad = 0;
+    for (int j = 0; j < kPerThread; ++j) {
+        const int64_t cl = first + threadIdx.x + (int64_t)j * kLevelThreads;
+        if (cl >= sg.n_cubes) break;
+        const int64_t c = sg.cube_base + cl;
+        const double2* P = a.partial + sg.part_base + cl * (int64_t)n1 * nch;
+        double sum = 0.0;
+        for (int t = 0; t < n1; ++t) {
+            double S1 = 0.0, S2 = 0.0;
+            for (int ch = 0; ch < nch; ++ch) {
+                const double2 v = P[t * nch + ch];
+                S1 += v.x;
+                S2 += v.y;
+            }
+            if (a.tr_S1) {
+                a.tr_S1[c * n1 + t] = S1;
+                a.tr_S2[c * n1 + t] = S2;
+            }
+            sum += V * (S1 / N);
+        }
+        const double m = sum / (double)n1;
+        double ss = 0.0;
+        for (int t = 0; t < n1; ++t) {
+            double S1 = 0.0;
+            for (int ch = 0; ch < nch; ++ch) S1 += P[t * nch + ch].x;
+            const double d = V * (S1 / N) - m;
+            ss += d * d;
+        }
+        const double s = sqrt(ss / (double)n1);
+        a.m[c] = m;
+        a.s[c] = s;
+        sum_s += s;
+        bad |= !(isfinite(m) && isfinite(s));
+    }
+    const double tot = block_sum(sum_s, sh);
+    const int any_bad = __syncthreads_or(bad);
+    if (threadIdx.x == 0) {
+        a.tiles[tile].sum_s = tot;
+        a.tiles[tile].nonfinite = any_bad;
+    }
+}
+
+// ---- threshold: mean of s, then std of s, per segment ----------------------
+__global__ __launch_bounds__(kLevelThreads) void seg_mean_kernel(const LevelArgs a)
+{
+    __shared__ double sh[kWaves];
+    const Segment& sg = a.segs[blockIdx.x];
+    if (!sg.need_thr) return;
+    double v = 0.0;
+    for (int64_t t = threadIdx.x; t < sg.n_tiles; t += kLevelThreads) v += a.tiles[sg.tile_base + t].sum_s;
+    const double tot = block_sum(v, sh);
+    if (threadIdx.x == 0) a.stats[blockIdx.x].mu = tot / (double)sg.n_cubes;
+}
+
+__global__ __launch_bounds__(kLevelThreads) void tile_sqdev_kernel(const LevelArgs a)
+{
+    __shared__ double sh[kWaves];
+    const int64_t tile = blockIdx.x;
+    const int si = seg_of_tile(a.segs, a.n_segs, tile);
+    const Segment& sg = a.segs[si];
+    if (!sg.need_thr) return;
+    const double mu = a.stats[si].mu;
+    const int64_t first = (tile - sg.tile_base) * kTileCubes;
+    double acc = 0.0;
+    for (int j = 0; j < kPerThread; ++j) {
+        const int64_t cl = first + threadIdx.x + (int64_t)j * kLevelThreads;
+        if (cl >= sg.n_cubes) break;
+        const double d = a.s[sg.cube_base + cl] - mu;
+        acc += d * d;
+    }
+    const double tot = block_sum(acc, sh);
+    if (threadIdx.x == 0) a.tiles[tile].sum_sq = tot;
+}
+
+__global__ __launch_bounds__(kLevelThreads) void seg_thr_kernel(const LevelArgs a)
+{
+    __shared__ double sh[kWaves];
+    const Segment& sg = a.segs[blockIdx.x];
+    if (!sg.need_thr) return;
+    double v = 0.0;
+    for (int64_t t = threadIdx.x; t < sg.n_tiles; t += kLevelThreads) v += a.tiles[sg.tile_base + t].sum_sq;
+    const double tot = block_sum(v, sh);
+    if (threadIdx.x == 0) {
+        const double sd = sqrt(tot / (double)sg.n_cubes);
+        a.stats[blockIdx.x].sd = sd;
+        a.stats[blockIdx.x].thr = a.stats[blockIdx.x].mu + a.slots[sg.slot].sigma_mult * sd;
+    }
+}
+
+// ---- selection: split = s > thr; accepted and selected sums per tile -------
+__global__ __launch_bounds__(kLevelThreads) void tile_select_kernel(const LevelArgs a)
+{
+    __shared__ double sh[kWaves];
+    __shared__ int64_t shi[kWaves];
+    const int64_t tile = blockIdx.x;
+    const int si = seg_of_tile(a.segs, a.n_segs, tile);
+    const Segment& sg = a.segs[si];
+    const bool thr_on = sg.need_thr != 0;
+    const double thr = thr_on ? a.stats[si].thr : 0.0;
+    const int64_t first = (tile - sg.tile_base) * kTileCubes;
+    double accM = 0.0, accS2 = 0.0, selM = 0.0, selS2 = 0.0, margin = DBL_MAX;
+    int64_t nsel = 0;
+    for (int j = 0; j < kPerThread; ++j) {
+        const int64_t cl = first + threadIdx.x + (int64_t)j * kLevelThreads;
+        if (cl >= sg.n_cubes) break;
+        const int64_t c = sg.cube_base + cl;
+        const double m = a.m[c], s = a.s[c];
+        const bool sel = thr_on && (s > thr);
+        a.sel[c] = sel ? 1 : 0;
+        if (sel) {
+            selM += m;
+            selS2 += s * s;
+            ++nsel;
+        } else {
+            accM += m;
+            accS2 += s * s;
+        }
+        if (thr_on && thr > 0.0) margin = fmin(margin, fabs(s - thr) / thr);
+    }
+    const double tAccM = block_sum(accM, sh);
+    const double tAccS2 = block_sum(accS2, sh);
+    const double tSelM = block_sum(selM, sh);
+    const double tSelS2 = block_sum(selS2, sh);
+    const double tMargin = block_min(margin, sh);
+    const int64_t tSel = block_sum_i(nsel, shi);
+    if (threadIdx.x == 0) {
+        TileRec& T = a.tiles[tile];
+        T.accM = tAccM;
+        T.accS2 = tAccS2;
+        T.selM = tSelM;
+        T.selS2 = tSelS2;
+        T.min_margin = tMargin;
+        T.n_sel = tSel;
+    }
+}
+
+// ---- per segment: totals, stop rules, rank base of every tile --------------
+__global__ __launch_bounds__(kLevelThreads) void seg_decide_kernel(const LevelArgs a)
+{
+    __shared__ double sh[kWaves];
+    __shared__ int64_t shi[kWaves];
+    __shared__ int shf[kWaves];
+    const int si = blockIdx.x;
+    const Segment& sg = a.segs[si];
+    const SlotDesc& sd = a.slots[sg.slot];
+    double accM = 0.0, accS2 = 0.0, selM = 0.0, selS2 = 0.0, margin = DBL_MAX;
+    int64_t nsel = 0;
+    int bad = 0;
+    for (int64_t t = threadIdx.x; t < sg.n_tiles; t += kLevelThreads) {
+        const TileRec& T = a.tiles[sg.tile_base + t];
+        accM += T.accM;
+        accS2 += T.accS2;
+        selM += T.selM;
+        selS2 += T.selS2;
+        margin = fmin(margin, T.min_margin);
+        nsel += T.n_sel;
+        bad |= T.nonfinite;
+    }
+    accM = block_sum(accM, sh);
+    accS2 = block_sum(accS2, sh);
+    selM = block_sum(selM, sh);
+    selS2 = block_sum(selS2, sh);
+    margin = block_min(margin, sh);
+    nsel = block_sum_i(nsel, shi);
+    bad = __syncthreads_or(bad);
+
+    // exclusive prefix of the tiles' selection counts (rank base for spawn)
+    int64_t carry = 0;
+    for (int64_t t0 = 0; t0 < sg.n_tiles; t0 += kLevelThreads) {
+        const int64_t t = t0 + threadIdx.x;
+        const int64_t v = t < sg.n_tiles ? a.tiles[sg.tile_base + t].n_sel : 0;
+        // inclusive wave scan
+        int64_t x = v;
+        const int lane = threadIdx.x & 63;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const int64_t y = __shfl_up(x, off, 64);
+            if (lane >= off) x += y;
+        }
+        __syncthreads();
+        if (lane == 63) shi[threadIdx.x >> 6] = x;
+        __syncthreads();
+        int64_t base = carry;
+        int64_t chunk = 0;
+        for (int w = 0; w < kWaves; ++w) {
+            if (w < (threadIdx.x >> 6)) base += shi[w];
+            chunk += shi[w];
+        }
+        if (t < sg.n_tiles) a.tiles[sg.tile_base + t].sel_prefix = base + x - v;
+        carry += chunk;
+    }
+    (void)shf;
+
+    if (threadIdx.x == 0) {
+        SegStats& S = a.stats[si];
+        const double2 prev = a.prev_tot[si];
+        if (!sg.need_thr) {
+            S.mu = S.sd = S.thr = __builtin_nan("");
+        }
+        S.min_margin = margin;
+        S.accM = accM;
+        S.accS2 = accS2;
+        S.selM = selM;
+        S.selS2 = selS2;
+        S.n_sel = nsel;
+        S.nonfinite = bad;
+        int32_t dec;
+        double totM = prev.x + accM, totS2 = prev.y + accS2;
+        if (!sg.need_thr || nsel == 0) {
+            dec = kDone;
+        } else {
+            const double runM = totM + selM, runS2 = totS2 + selS2;
+            if (sd.rtol > 0.0 && sqrt(runS2 / (double)(sd.trials - 1)) <= sd.rtol * fabs(runM)) {
+                dec = kRtolMet;
+            } else if (((uint64_t)nsel << sd.dim) > (uint64_t)sd.max_cubes) {
+                dec = kTruncated;
+            } else {
+                dec = kSplit;
+            }
+            if (dec != kSplit) {
+                totM = runM;
+                totS2 = runS2;
+            }
+        }
+        S.decision = dec;
+        S.totM = totM;
+        S.totS2 = totS2;
+    }
+}
+
+// ---- spawn: children of the selected cubes, in list order ------------------
+__global__ __launch_bounds__(kLevelThreads) void spawn_kernel(const LevelArgs a)
+{
+    __shared__ uint64_t list[kTileCubes];
+    __shared__ int shf[kWaves];
+    const int64_t tile = blockIdx.x;
+    const int si = seg_of_tile(a.segs, a.n_segs, tile);
+    const Segment& sg = a.segs[si];
+    if (!sg.do_split) return;
+    const int D = a.slots[sg.slot].dim;
+    const int64_t first = (tile - sg.tile_base) * kTileCubes;
+    int base = 0;
+    for (int j = 0; j < kPerThread; ++j) {
+        const int64_t cl = first + threadIdx.x + (int64_t)j * kLevelThreads;
+        const int flag = (cl < sg.n_cubes) ? a.sel[sg.cube_base + cl] : 0;
+        int total;
+        const int pos = block_excl_scan_flag(flag, shf, &total);
+        if (flag) list[base + pos] = a.uid[sg.cube_base + cl];
+        base += total;
+    }
+    __syncthreads();
+    const int64_t n_writes = (int64_t)base << D;
+    const uint64_t mask = (1ull << D) - 1ull;
+    uint64_t* out = a.next_uid + sg.child_base + (a.tiles[tile].sel_prefix << D);
+    for (int64_t w = threadIdx.x; w < n_writes; w += kLevelThreads) {
+        const uint64_t parent = list[w >> D];
+        out[w] = (parent << D) | ((uint64_t)w & mask);
+    }
+}
+
+// ---- roots: uid = r for the d^D cubes of a newly admitted integral ----------
+__global__ __launch_bounds__(kLevelThreads) void roots_kernel(const RootArgs a)
+{
+    const int si = blockIdx.x / a.blocks_per_seg;
+    const int part = blockIdx.x % a.blocks_per_seg;
+    const Segment& sg = a.segs[si];
+    for (int64_t r = (int64_t)part * kLevelThreads + threadIdx.x; r < sg.n_cubes;
+         r += (int64_t)a.blocks_per_seg * kLevelThreads)
+        a.uid[sg.cube_base + r] = (uint64_t)r;
+}
+
+// ---- debug entry points ------------------------------------------------------
+__global__ void debug_philox_kernel(uint32_t k0, uint32_t k1, const uint32_t* ctr, uint32_t* out, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const U4 r = philox4x32_10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], k0, k1);
+    out[4 * i] = r.x;
+    out[4 * i + 1] = r.y;
+    out[4 * i + 2] = r.z;
+    out[4 * i + 3] = r.w;
+}
+
+__global__ void debug_points_kernel(const SlotDesc* sdp, int level, uint64_t uid, int trial, int64_t s0, int64_t n,
+                                    double* x)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const SlotDesc& sd = *sdp;
+    const int D = sd.dim;
+    double lo[kMaxDim], h[kMaxDim];
+    cube_corner(sd, D, level, uid, lo, h);
+    const int64_t s = s0 + k;
+    for (int i = 0; i < D; ++i) {
+        const uint64_t nw = (uint64_t)s * (uint64_t)D + (uint64_t)i;
+        const U4 r = philox4x32_10((uint32_t)(nw >> 2), (uint32_t)trial | ((uint32_t)level << 8), (uint32_t)uid,
+                                   (uint32_t)(uid >> 32), (uint32_t)sd.seed, (uint32_t)(sd.seed >> 32));
+        const uint32_t words[4] = {r.x, r.y, r.z, r.w};
+        const uint32_t w = words[nw & 3u];
+        x[k * D + i] = fma(ldexp(h[i], -24), (double)((w >> 8) | 1u), lo[i]);
+    }
+}
+
+} // namespace
+
+hipError_t launch_finalize(const LevelArgs& a, hipStream_t st)
+{
+    if (a.n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)a.n_tiles), dim3(kLevelThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_threshold(const LevelArgs& a, hipStream_t st)
+{
+    if (a.n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(seg_mean_kernel, dim3(a.n_segs), dim3(kLevelThreads), 0, st, a);
+    hipLaunchKernelGGL(tile_sqdev_kernel, dim3((unsigned)a.n_tiles), dim3(kLevelThreads), 0, st, a);
+    hipLaunchKernelGGL(seg_thr_kernel, dim3(a.n_segs), dim3(kLevelThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const LevelArgs& a, hipStream_t st)
+{
+    if (a.n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(tile_select_kernel, dim3((unsigned)a.n_tiles), dim3(kLevelThreads), 0, st, a);
+    hipLaunchKernelGGL(seg_decide_kernel, dim3(a.n_segs), dim3(kLevelThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_spawn(const LevelArgs& a, hipStream_t st)
+{
+    if (a.n_tiles <= 0) return hipSuccess;
+    hipLaunchKernelGGL(spawn_kernel, dim3((unsigned)a.n_tiles), dim3(kLevelThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_roots(const RootArgs& a, hipStream_t st)
+{
+    if (a.n_segs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(roots_kernel, dim3(a.n_segs * a.blocks_per_seg), dim3(kLevelThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_philox(uint32_t k0, uint32_t k1, const uint32_t* ctr, uint32_t* out, int64_t n,
+                               hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(debug_philox_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, k0, k1, ctr, out,
+                       n);
+    return hipGetLastError();
+}
+
+hipError_t launch_debug_points(const SlotDesc* sd, int level, uint64_t uid, int trial, int64_t s0, int64_t n,
+                               double* x, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(debug_points_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, sd, level, uid,
+                       trial, s0, n, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample(int integrand, int dim, int eval, int grid, hipStream_t st, const SampleArgs& a)
+{
+    switch (integrand) {
+    case 0: return launch_sample_0(dim, eval, grid, st, a);
+    case 1: return launch_sample_1(dim, eval, grid, st, a);
+    case 2: return launch_sample_2(dim, eval, grid, st, a);
+    case 3: return launch_sample_3(dim, eval, grid, st, a);
+    case 4: return launch_sample_4(dim, eval, grid, st, a);
+    case 5: return launch_sample_5(dim, eval, grid, st, a);
+    case 6: return launch_sample_6(dim, eval, grid, st, a);
+    case 7: return launch_sample_7(dim, eval, grid, st, a);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+const void* sample_kernel_ptr(int integrand, int dim, int eval)
+{
+    switch (integrand) {
+    case 0: return sample_kernel_ptr_0(dim, eval);
+    case 1: return sample_kernel_ptr_1(dim, eval);
+    case 2: return sample_kernel_ptr_2(dim, eval);
+    case 3: return sample_kernel_ptr_3(dim, eval);
+    case 4: return sample_kernel_ptr_4(dim, eval);
+    case 5: return sample_kernel_ptr_5(dim, eval);
+    case 6: return sample_kernel_ptr_6(dim, eval);
+    case 7: return sample_kernel_ptr_7(dim, eval);
+    default: return nullptr;
+    }
+}
+
+} // namespace zmc

@@ -1,0 +1,116 @@
+"""CPU-side checks of the C ABI: the library loads, exports every function
+that include/zmc.h declares, its structs match the binding, and argument
+errors are reported without touching the GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1902_07916_amd import _abi
+    if not os.path.exists(_abi.LIB_PATH):
+        from paper_1902_07916_amd import build
+        build.build()
+    return _abi.load()
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "zmc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(zmc_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    from paper_1902_07916_amd import _abi
+    assert set(_abi.EXPORTS) == set(names)
+
+
+def test_struct_layout(lib):
+    from paper_1902_07916_amd import _abi
+    for i, T in enumerate((_abi.Result, _abi.Request, _abi.Config, _abi.Trace)):
+        assert lib.zmc_struct_size(i) == C.sizeof(T)
+    assert lib.zmc_struct_size(9) == -1
+    assert b"gfx950" in lib.zmc_version()
+
+
+def _req(**kw):
+    from paper_1902_07916_amd import make_request
+    base = dict(integrand="gauss", params=[0.2, 1.0, 0.0, 0.0], lower=-1.0, upper=[1.0, 1.0], divisions=4,
+                samples=64, trials=3, max_depth=1, sigma_mult=1.0, seed=1)
+    base.update(kw)
+    return make_request(**base)
+
+
+def test_invalid_arguments_are_rejected_before_any_device_call(lib):
+    from paper_1902_07916_amd import _abi
+    bad = [dict(params=[0.2, 1.0]), dict(divisions=0), dict(samples=0), dict(trials=1), dict(trials=256),
+           dict(max_depth=16), dict(max_depth=-1), dict(sigma_mult=-1.0), dict(sigma_mult=float("inf")),
+           dict(lower=1.0), dict(upper=[float("nan"), 1.0]), dict(integrand=42), dict(eval=7),
+           dict(integrand="monomial", params=[1.5, 2.0]), dict(rtol=-1.0),
+           dict(samples=(1 << 33) + 4), dict(divisions=2, max_depth=15, params=[0.2, 1.0] + [0.0] * 2,
+                                             lower=[-1.0] * 2, upper=[1.0] * 2, samples=4, trials=2) | {"divisions": 3000000},
+           dict(max_cubes_per_level=8)]
+    for b in bad:
+        r = _req(**b)
+        out = _abi.Result()
+        rc = lib.zmc_integrate_request(C.byref(r), None, C.byref(out), None)
+        assert rc == _abi.EINVAL, b
+        assert out.status == _abi.EINVAL
+        assert lib.zmc_strerror(rc)
+
+
+def test_valid_request_without_init(lib):
+    from paper_1902_07916_amd import _abi
+    out = _abi.Result()
+    rc = lib.zmc_integrate_request(C.byref(_req()), None, C.byref(out), None)
+    assert rc == _abi.ENOINIT
+    t = C.c_uint64()
+    assert lib.zmc_submit(C.byref(_req()), C.byref(t)) == _abi.ENOINIT
+    assert lib.zmc_poll(1, C.byref(out), 0) == _abi.ENOINIT
+
+
+def test_init_rejects_bad_config(lib):
+    from paper_1902_07916_amd import _abi
+    assert lib.zmc_init(None) == _abi.EINVAL
+    cfg = _abi.Config()
+    cfg.arena = None
+    assert lib.zmc_init(C.byref(cfg)) == _abi.EINVAL
+    cfg.arena = 256
+    cfg.arena_bytes = 1 << 20
+    assert lib.zmc_init(C.byref(cfg)) == _abi.EINVAL
+    cfg.arena_bytes = 1 << 30
+    cfg.arena = 257
+    assert lib.zmc_init(C.byref(cfg)) == _abi.EINVAL
+
+
+def test_integrate_scalar_entry_checks(lib):
+    from paper_1902_07916_amd import _abi
+    out = _abi.Result()
+    lo = (C.c_double * 2)(0.0, 0.0)
+    hi = (C.c_double * 2)(1.0, 1.0)
+    rc = lib.zmc_integrate(1, None, 0, 2, lo, hi, 2, 16, 3, 1, 1.0, 1, 0, None, C.byref(out))
+    assert rc == _abi.ENOINIT
+    rc = lib.zmc_integrate(1, None, 0, 2, None, hi, 2, 16, 3, 1, 1.0, 1, 0, None, C.byref(out))
+    assert rc == _abi.EINVAL
+
+
+def test_workloads_are_deterministic():
+    from paper_1902_07916_amd import workloads as W
+    a = W.genz_batch(n=32)
+    b = W.genz_batch(n=32)
+    assert a == b
+    assert all(2 <= len(r["lower"]) <= 12 and r["divisions"] ** len(r["lower"]) <= 100_000 for r in a)
+    s = W.serving_stream(duration=2.0)
+    assert 300 < len(s) < 500 and all(3 <= len(r["lower"]) <= 12 for _, r in s)
+    assert all(1e-5 <= r["rtol"] <= 1e-3 for _, r in s)
+    assert all(r["divisions"] ** len(r["lower"]) <= 4096 for _, r in s)
