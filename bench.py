@@ -24,45 +24,53 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X figures used by the roofline (vendor specification)
+# MI355X figures used by the roofline (vendor specification: 256 CUs at
+# 2.4 GHz; FP32 157.3 TFLOP/s = 128 FMA lanes per CU per clock).
 N_CU = 256
 CLOCK_HZ = 2.4e9
-LANES_PER_CU_CLK = 64            # 4 SIMDs x 16 lanes: one wave64 VALU op per SIMD per 4 clocks
-VALU_PEAK = N_CU * CLOCK_HZ * LANES_PER_CU_CLK   # 3.93e13 lane-cycles/s
-FP32_PEAK_FLOPS = 157.3e12       # packed FP32 FMA
+SLOTS_PER_CU_CLK = 128
+VALU_PEAK = N_CU * CLOCK_HZ * SLOTS_PER_CU_CLK   # 7.86e13 VALU slots/s
+FP32_PEAK_FLOPS = 157.3e12
 FP64_PEAK_FLOPS = 78.6e12
 
-# Issue cost, in lane-cycles per lane, of the instruction forms the sampling
-# kernel needs (quarter-rate ops take 4); measured on gfx950 with a
-# throughput probe (see the design notes).
-COST = dict(mad_u64=4.0, bitop3=1.0, alu=1.0, fma32=1.0, trans32=4.0, fp64=1.0)
+# Issue cost in VALU slots (1 slot = one lane of the 128-lane/clock/CU FP32
+# rate) of each instruction class, from gfx950's issue rates: FP32
+# add/mul/FMA 128 lanes/clk/CU; 32-bit integer and bitwise ops, the 32x32->64
+# v_mad_u64_u32, FP64 ops and conversions 64; transcendentals (exp2, sin,
+# rcp) 32.  A throughput probe measured 107, 64, 53, 56 and 31 respectively.
+SLOT = dict(fp32=1.0, int=2.0, fp64=2.0, trans=4.0)
 
 
-def valu_cycles_per_sample(integrand: str, D: int, eval_: str) -> dict:
-    """Minimal VALU lane-cycles per sample of the method on this ISA.
+def valu_slots_per_sample(integrand: str, D: int, eval_: str) -> dict:
+    """Minimal VALU slots per sample the method needs on this ISA.
 
-    RNG: D/4 Philox4x32-10 blocks per sample; a block is 10 rounds of two
-    32x32->64 products and two 3-input XORs, of which the first round's
-    product of the (wave-uniform) counter word 2 and its XOR are scalar work
-    -> 18 v_mad_u64_u32 + 18 v_bitop3_b32 per block.  Map: one bit-op per
-    coordinate (+ the FMA that places it in the cube).  Integrand and the
-    FP64 accumulation (f, f^2) as listed per family."""
+    RNG: D/4 Philox4x32-10 blocks per sample.  A block is 10 rounds of two
+    32x32->64 products and two 3-input XORs; with counter words 1-3 uniform
+    over a wave the first round's product of word 2, its XOR and the second
+    round's product of word 0 are scalar work: 18 v_mad_u64_u32 + 19
+    v_bitop3_b32/v_xor_b32 per block.  Mapping: one v_alignbit_b32 per
+    coordinate plus the FMA that places it.  Integrand and the FP64
+    accumulation of f and f^2 per family."""
     blocks = D / 4.0
-    rng = blocks * (18 * COST["mad_u64"] + 18 * COST["bitop3"])
+    rng = blocks * 37 * SLOT["int"]
     if eval_ == "fp32":
-        mapping = D * (COST["alu"] + COST["fma32"])
-        if integrand == "sin_sum":
-            f = 13 * COST["alu"]                       # sin(2 pi r) reduction + odd polynomial
-        elif integrand == "gauss":
-            f = D * COST["fma32"] + COST["fma32"] + COST["trans32"] + COST["fma32"]  # t^2 sum, scale, exp2, A*
+        mapping = D * (SLOT["int"] + SLOT["fp32"])
+        if integrand in ("sin_sum", "genz_osc"):
+            # + low part of the cube phase; r - rint(r), fold to [-1/4, 1/4]
+            # (cmp, copysign, sub, select), t^2, 6 FMA, *t
+            f = 8 * SLOT["fp32"] + 3 * SLOT["int"] + 2 * SLOT["fp32"]
+        elif integrand in ("gauss", "genz_gauss"):
+            f = D * SLOT["fp32"] + 2 * SLOT["fp32"] + SLOT["trans"]      # t^2 sum, scale, exp2, A*
+        elif integrand == "genz_ppeak":
+            f = 2 * D * SLOT["fp32"] + SLOT["trans"]
         else:
-            f = 2 * D * COST["fma32"] + COST["trans32"]
-        acc = 3 * COST["fp64"]                         # cvt, add, fma
-        flops32 = 2 * D + (16 if integrand == "sin_sum" else 2 * D + 2)
+            f = 5 * SLOT["fp32"] + SLOT["trans"]
+        acc = 3 * SLOT["fp64"]                                            # cvt, add, fma
+        flops32 = 2 * D + 2 * D + 4
     else:
-        mapping = D * (3 * COST["alu"] + COST["fp64"])  # shift/or, cvt, fma
-        f = (D + 30) * COST["fp64"]                    # sum + FP64 sin / exp
-        acc = 2 * COST["fp64"]
+        mapping = D * (2 * SLOT["int"] + 2 * SLOT["fp64"])               # shift|1, cvt, fma
+        f = D * SLOT["fp64"] + 30 * SLOT["fp64"]                         # sum + FP64 sin/exp
+        acc = 2 * SLOT["fp64"]
         flops32 = 0
     return dict(rng=rng, map=mapping, f=f, acc=acc, total=rng + mapping + f + acc, fp32_flops=flops32)
 
@@ -75,6 +83,35 @@ WORKLOADS = {
     "gauss4d": ("gauss4d", "gauss", "exp(-|x|^2/(2*0.2^2)) on [-1,1]^4, d=4 (256 cubes), N=4096, n1=5, "
                 "max_depth=1, sigma_mult=1, seed=1"),
 }
+
+
+KERNEL_SOURCES = ("paper_1902_07916_amd/csrc/zmc_sample.hip", "paper_1902_07916_amd/csrc/zmc_integrands.hpp",
+                  "paper_1902_07916_amd/csrc/zmc_device.hpp", "paper_1902_07916_amd/csrc/zmc_kernels.hpp")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sample_kernel.json")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per launch of the sampling kernel from the committed
+    FETCH_SIZE / WRITE_SIZE runs, or None when the kernel sources changed
+    since those counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = t.get(workload)
+    if not e or e.get("source_hash") != kernel_source_hash():
+        return None
+    return e["bytes_per_launch"]
 
 
 def cpu_baseline(w: dict, seconds: float) -> dict:
@@ -95,15 +132,88 @@ def cpu_baseline(w: dict, seconds: float) -> dict:
                       % (n - 1, w["trials"], w["samples"], samples, dt)}
 
 
+def percentile(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q
+    f = int(math.floor(k))
+    c = min(f + 1, len(xs) - 1)
+    return xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def run_batch(a) -> dict:
+    """Batched workload: n independent Genz integrals (D in 2..12) per step,
+    all levels of all of them in shared launches."""
+    import torch
+    from paper_1902_07916_amd import Integrator, request_from_dict, workloads
+    ws = workloads.genz_batch(n=a.batch_n, max_cubes_per_level=a.batch_cap)
+    reqs = [request_from_dict(w) for w in ws]
+    zi = Integrator(arena_bytes=int(a.arena_gib * (1 << 30)), max_slots=max(8192, len(reqs)))
+    for _ in range(a.warmup):
+        zi.integrate_batch(reqs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = [zi.integrate_batch(reqs) for _ in range(a.steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    zi.close()
+    last = outs[-1]
+    samples = sum(r.n_samples for o in outs for r in o)
+    k_ms = sum(sum(r.sample_ms_per_level) for r in last)  # per-integral copies of the shared level time
+    return {"integrals_per_s": len(reqs) * a.steps / dt, "samples_per_s": samples / dt,
+            "ms_per_step": dt * 1e3 / a.steps, "n_integrals": len(reqs),
+            "status_ok": sum(r.status == 0 for r in last), "truncated": sum(bool(r.flags & 1) for r in last),
+            "cubes_total": sum(r.n_cubes for r in last), "samples_per_step": samples // a.steps}
+
+
+def run_serve(a) -> dict:
+    """Serving workload: a Poisson stream of requests submitted in real time;
+    latency = submit -> result visible to poll."""
+    from paper_1902_07916_amd import Integrator, request_from_dict, workloads
+    stream = workloads.serving_stream(rate=a.rate, duration=a.duration)
+    reqs = [request_from_dict(w) for _, w in stream]
+    zi = Integrator(arena_bytes=int(a.arena_gib * (1 << 30)), serve=True)
+    # warm the kernels of every (integrand, D) bucket once
+    for rq in reqs[:64]:
+        zi.integrate_request(rq)
+    t0 = time.perf_counter()
+    tickets = []
+    for (t, _), rq in zip(stream, reqs):
+        while True:
+            now = time.perf_counter() - t0
+            if now >= t:
+                break
+            time.sleep(min(0.001, t - now))
+        tickets.append(zi.submit(rq))
+    res = [zi.poll(tk, wait=True) for tk in tickets]
+    dt = time.perf_counter() - t0
+    st = zi.serve_stats()
+    zi.close()
+    lat = [r.latency_ms for r in res]
+    return {"requests": len(res), "offered_rate": a.rate, "duration_s": a.duration, "wall_s": dt,
+            "integrals_per_s": len(res) / dt, "p50_ms": percentile(lat, 0.5), "p99_ms": percentile(lat, 0.99),
+            "max_ms": max(lat), "rtol_met": sum(bool(r.flags & 2) for r in res) / len(res),
+            "status_ok": sum(r.status == 0 for r in res), "samples": sum(r.n_samples for r in res),
+            "levels_stepped": st["levels"]}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sin6d", choices=sorted(WORKLOADS))
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve"])
     ap.add_argument("--no-fp64", action="store_true", help="skip timing the plain FP64 path")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--arena-gib", type=float, default=48.0)
+    ap.add_argument("--batch-n", type=int, default=4096)
+    ap.add_argument("--batch-cap", type=int, default=1 << 20)
+    ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--duration", type=float, default=60.0)
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="first copy a buffer of this size with a plain copy kernel (calibrates HBM byte counters)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the work would shard by whole "
@@ -117,6 +227,18 @@ def main(argv=None) -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
+    if a.mode == "batch":
+        print(json.dumps({"mode": "batch", **run_batch(a)}))
+        return 0
+    if a.mode == "serve":
+        print(json.dumps({"mode": "serve", **run_serve(a)}))
+        return 0
+    if a.copy_calibration_mib > 0:
+        src = torch.ones(a.copy_calibration_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     gen, integrand, desc = WORKLOADS[a.workload]
     w32 = getattr(workloads, gen)(eval="fp32")
     w64 = getattr(workloads, gen)(eval="fp64")
@@ -138,13 +260,14 @@ def main(argv=None) -> int:
     k_ms = sum(sum(x.sample_ms_per_level) for x in results)
     k_launches = sum(sum(x.sample_launches_per_level) for x in results)
     k_samples = samples
-    cyc = valu_cycles_per_sample(integrand, D, "fp32")
+    cyc = valu_slots_per_sample(integrand, D, "fp32")
     achieved = k_samples * cyc["total"] / (k_ms * 1e-3)
-    roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK, "unit": "VALU lane-cycles/s",
-                "frac": achieved / VALU_PEAK, "traffic": None,
+    roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK, "unit": "VALU slots/s",
+                "frac": achieved / VALU_PEAK, "traffic": measured_traffic(a.workload),
                 "kernel": "sample_kernel<%s,D=%d,FP32>" % (integrand, D),
                 "avg_launch_ms": k_ms / max(k_launches, 1), "launches": k_launches,
-                "cycles_per_sample": cyc, "kernel_samples_per_s": k_samples / (k_ms * 1e-3),
+                "slots_per_sample": cyc, "kernel_samples_per_s": k_samples / (k_ms * 1e-3),
+                "roofline_samples_per_s": VALU_PEAK / cyc["total"],
                 "fp32_flop_frac": k_samples * cyc["fp32_flops"] / (k_ms * 1e-3) / FP32_PEAK_FLOPS}
 
     out = {"metric": "integrand samples/sec + % FP32 VALU peak vs plain FP64; p50/p99 latency at QPS",

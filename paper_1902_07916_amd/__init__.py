@@ -152,6 +152,8 @@ class Integrator:
             self._open = False
             if Integrator._active is self:
                 Integrator._active = None
+            self.arena = None
+            self.serve_stream = None
 
     def __enter__(self):
         return self

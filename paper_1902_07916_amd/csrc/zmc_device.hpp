@@ -113,6 +113,48 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
     return U4{c0, c1, c2, c3};
 }
 
+// K Philox4x32-10 blocks whose counters differ only in word 0, computed in
+// lockstep round by round: the 2K products of a round are independent, which
+// hides the latency of v_mad_u64_u32 even at low occupancy, and the work on
+// the shared (wave-uniform) counter words 1-3 in the first rounds is done
+// once for all K blocks.  out[4*b + j] is word j of block b.
+template <int K>
+__device__ __forceinline__ void philox4x32_10_lockstep(const uint32_t (&c0)[K], uint32_t c1, uint32_t c2,
+                                                       uint32_t c3, uint32_t k0, uint32_t k1, uint32_t (&out)[4 * K])
+{
+    uint32_t x0[K], x1[K], x2[K], x3[K];
+#pragma unroll
+    for (int b = 0; b < K; ++b) {
+        x0[b] = c0[b];
+        x1[b] = c1;
+        x2[b] = c2;
+        x3[b] = c3;
+    }
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+#pragma unroll
+        for (int b = 0; b < K; ++b) {
+            const uint64_t p0 = (uint64_t)x0[b] * 0xD2511F53u;
+            const uint64_t p1 = (uint64_t)x2[b] * 0xCD9E8D57u;
+            const uint32_t n0 = xor3((uint32_t)(p1 >> 32), x1[b], k0);
+            const uint32_t n2 = xor3((uint32_t)(p0 >> 32), x3[b], k1);
+            x1[b] = (uint32_t)p1;
+            x3[b] = (uint32_t)p0;
+            x0[b] = n0;
+            x2[b] = n2;
+        }
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+#pragma unroll
+    for (int b = 0; b < K; ++b) {
+        out[4 * b + 0] = x0[b];
+        out[4 * b + 1] = x1[b];
+        out[4 * b + 2] = x2[b];
+        out[4 * b + 3] = x3[b];
+    }
+}
+
 // u = (2*(w>>9)+1) * 2^-24, exact in FP64.
 __device__ __forceinline__ double uniform_f64(uint32_t w)
 {

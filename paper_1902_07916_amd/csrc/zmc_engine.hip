@@ -51,7 +51,7 @@ TileTable::TileTable()
 {
     for (int f = 0; f < 8; ++f)
         for (int d = 0; d <= ZMC_MAX_DIM; ++d)
-            for (int e = 0; e < 2; ++e) groups[f][d][e] = 4;
+            for (int e = 0; e < 2; ++e) groups[f][d][e] = 16;
 }
 
 // Tuning file: a JSON object whose keys "integrand:dim:eval" map to the
@@ -138,9 +138,18 @@ void Engine::teardown()
     cap_cache_.clear();
 }
 
+// Chunk of one sampling unit: 4 * 256 * groups points, with groups the
+// smaller of the tile table's cap for the bucket and what N needs, so a
+// request's chunking depends only on its own parameters.
+int Engine::groups_of(const zmc_request& r) const
+{
+    const int64_t need = ceil_div(r.samples_per_cube, 4LL * kSampleThreads);
+    return (int)std::max<int64_t>(1, std::min<int64_t>(need, tiles_->get(r.integrand, r.dim, r.eval)));
+}
+
 int Engine::nch_of(const zmc_request& r) const
 {
-    const int64_t chunk = 4LL * kSampleThreads * tiles_->get(r.integrand, r.dim, r.eval);
+    const int64_t chunk = 4LL * kSampleThreads * groups_of(r);
     return (int)ceil_div(r.samples_per_cube, chunk);
 }
 
@@ -168,7 +177,7 @@ int Engine::fill_slot_desc(int slot, const zmc_request& r, hipStream_t st)
     d.divisions = r.divisions_per_axis;
     d.trials = r.trials;
     d.max_depth = r.max_depth;
-    d.groups = tiles_->get(r.integrand, r.dim, r.eval);
+    d.groups = groups_of(r);
     d.nch = nch_of(r);
     d.samples = r.samples_per_cube;
     d.max_cubes = r.max_cubes_per_level > 0 ? r.max_cubes_per_level : ZMC_DEFAULT_MAX_CUBES;
@@ -309,7 +318,7 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
     }
     int nb = 0;
     struct Launch {
-        int off, count, integrand, dim, eval, groups;
+        int off, count, integrand, dim, eval;
         int64_t units;
     };
     std::vector<Launch> launches;
@@ -321,7 +330,6 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
         L.integrand = r0.integrand;
         L.dim = r0.dim;
         L.eval = r0.eval;
-        L.groups = tiles_->get(r0.integrand, r0.dim, r0.eval);
         int64_t u = 0;
         for (int i : kv.second) {
             const zmc_request& r = slots_[live[i].slot].req;
@@ -344,7 +352,6 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
         a.segs = d_segs_;
         a.bsegs = d_bsegs_ + L.off;
         a.n_bsegs = L.count;
-        a.groups = L.groups;
         a.total_units = L.units;
         a.uid = cur_uid;
         a.partial = partial;

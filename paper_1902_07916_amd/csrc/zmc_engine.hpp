@@ -65,9 +65,10 @@ private:
     size_t size_ = 0, lo_ = 0, hi_ = 0;
 };
 
-// Tile shape of the sampling kernel per (integrand, dim, eval): 4-point
-// groups per thread per chunk.  Fixed per build or tuning file, never by the
-// batch composition, so a request's result does not depend on its company.
+// Tile shape of the sampling kernel per (integrand, dim, eval): the cap on
+// 4-point groups per thread per chunk (default 16).  Fixed per build or
+// tuning file, never by the batch composition, so a request's result does
+// not depend on its company.
 struct TileTable {
     int groups[8][ZMC_MAX_DIM + 1][2];
     TileTable();
@@ -126,6 +127,7 @@ public:
     size_t reservation_bytes(const zmc_request& r) const;
     size_t budget_bytes() const { return arena_.size(); }
     int nch_of(const zmc_request& r) const;
+    int groups_of(const zmc_request& r) const;
 
 private:
     int fill_slot_desc(int slot, const zmc_request& r, hipStream_t st);

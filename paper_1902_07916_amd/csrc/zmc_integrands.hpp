@@ -47,6 +47,28 @@ __device__ __forceinline__ float sin_rev(float r)
 // frac(x) in FP64 for the per-cube phase offsets.
 __device__ __forceinline__ double frac64(double x) { return x - floor(x); }
 
+// A per-cube phase offset (revolutions) as a float pair hi + lo.
+__device__ __forceinline__ void split_phase(double r0, float& hi, float& lo)
+{
+    hi = (float)r0;
+    lo = (float)(r0 - (double)hi);
+}
+
+// Phase of a point in revolutions: r0 + sum m_i v_i in FP32.  The cube
+// offsets r0 form a lattice, so rounding r0 itself to FP32 would give errors
+// that correlate with the phases and do not average out over the domain (for
+// sin(sum x) over [0,10]^6, whose integral is 1.3e4 times smaller than that of
+// |f|, it biases the result by ~1e-4).  The low part therefore enters first,
+// where the rounding varies from point to point: fma(m_0, v_0, lo), then + hi.
+template <int D>
+__device__ __forceinline__ float phase_sum(const float* m, const float* v, float hi, float lo)
+{
+    float r = __builtin_fmaf(m[0], v[0], lo) + hi;
+#pragma unroll
+    for (int i = 1; i < D; ++i) r = __builtin_fmaf(m[i], v[i], r);
+    return r;
+}
+
 // Integer power by squaring (exponent known per launch, small).
 template <typename T>
 __device__ __forceinline__ T ipow(T x, int n)
@@ -118,7 +140,7 @@ struct Integrand<ZMC_SIN_SUM, D> {
         int dummy;
     };
     struct P32 {
-        float m[D], r0;
+        float m[D], r0_hi, r0_lo;
     };
     __device__ static void prep64(const SlotDesc&, P64&) {}
     __device__ static double f64(const P64&, const double* x)
@@ -135,15 +157,9 @@ struct Integrand<ZMC_SIN_SUM, D> {
             b += lo[i] - h[i] * kOneMinus;
             p.m[i] = (float)(h[i] * kInvTwoPi);
         }
-        p.r0 = (float)frac64(b * kInvTwoPi);
+        split_phase(frac64(b * kInvTwoPi), p.r0_hi, p.r0_lo);
     }
-    __device__ static float f32(const P32& p, const float* v)
-    {
-        float r = p.r0;
-#pragma unroll
-        for (int i = 0; i < D; ++i) r = __builtin_fmaf(p.m[i], v[i], r);
-        return sin_rev(r);
-    }
+    __device__ static float f32(const P32& p, const float* v) { return sin_rev(phase_sum<D>(p.m, v, p.r0_hi, p.r0_lo)); }
 };
 
 // ---- ZMC_GENZ_OSC: cos(2 pi u + sum c_i x_i) = sin(2 pi (u + 1/4 + sum c_i x_i / 2pi))
@@ -153,7 +169,7 @@ struct Integrand<ZMC_GENZ_OSC, D> {
         double c[D], ph;
     };
     struct P32 {
-        float m[D], r0;
+        float m[D], r0_hi, r0_lo;
     };
     __device__ static void prep64(const SlotDesc& sd, P64& p)
     {
@@ -175,15 +191,9 @@ struct Integrand<ZMC_GENZ_OSC, D> {
             b += c * (lo[i] - h[i] * kOneMinus) * kInvTwoPi;
             p.m[i] = (float)(c * h[i] * kInvTwoPi);
         }
-        p.r0 = (float)frac64(b);
+        split_phase(frac64(b), p.r0_hi, p.r0_lo);
     }
-    __device__ static float f32(const P32& p, const float* v)
-    {
-        float r = p.r0;
-#pragma unroll
-        for (int i = 0; i < D; ++i) r = __builtin_fmaf(p.m[i], v[i], r);
-        return sin_rev(r);
-    }
+    __device__ static float f32(const P32& p, const float* v) { return sin_rev(phase_sum<D>(p.m, v, p.r0_hi, p.r0_lo)); }
 };
 
 // ---- ZMC_GENZ_PPEAK: prod 1 / (c_i^-2 + (x_i - w_i)^2) ----------------------

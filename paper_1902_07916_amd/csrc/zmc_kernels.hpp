@@ -27,7 +27,7 @@ struct SampleArgs {
     const Segment* segs;
     const BSeg* bsegs;
     int32_t n_bsegs;
-    int32_t groups; // 4-sample groups per thread per chunk
+    int32_t pad;
     int64_t total_units;
     const uint64_t* uid;
     double2* partial;

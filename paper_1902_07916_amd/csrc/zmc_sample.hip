@@ -106,7 +106,7 @@ __global__ __launch_bounds__(kSampleThreads) void sample_kernel(const SampleArgs
         const uint32_t c1 = (uint32_t)trial | ((uint32_t)level << 8);
         const uint32_t c2 = (uint32_t)uid, c3 = (uint32_t)(uid >> 32);
         const int64_t N = sd.samples;
-        const int G = a.groups;
+        const int G = sd.groups;
         const int64_t g0 = (int64_t)chunk * G * kSampleThreads + tid;
 
         double S1 = 0.0, S2 = 0.0;
@@ -117,23 +117,20 @@ __global__ __launch_bounds__(kSampleThreads) void sample_kernel(const SampleArgs
                 const int64_t g = g0 + (int64_t)j * kSampleThreads;
                 const int64_t s0 = 4 * g;
                 if (s0 >= N) break;
+                const int nvalid = (int)min((int64_t)4, N - s0); // < 4 only in a ragged last group
                 uint32_t w[4 * D];
+                uint32_t ctr[D];
                 const uint32_t cb = (uint32_t)g * (uint32_t)D;
 #pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    const U4 r = philox4x32_10(cb + (uint32_t)k, c1, c2, c3, k0, k1);
-                    w[4 * k + 0] = r.x;
-                    w[4 * k + 1] = r.y;
-                    w[4 * k + 2] = r.z;
-                    w[4 * k + 3] = r.w;
-                }
+                for (int k = 0; k < D; ++k) ctr[k] = cb + (uint32_t)k;
+                philox4x32_10_lockstep<D>(ctr, c1, c2, c3, k0, k1, w);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     float v[D];
 #pragma unroll
                     for (int i = 0; i < D; ++i) v[i] = unit_interval_f32(w[q * D + i]);
                     float f = I::f32(p, v);
-                    f = (s0 + q < N) ? f : 0.0f;
+                    f = (q < nvalid) ? f : 0.0f;
                     const double fd = (double)f;
                     S1 += fd;
                     S2 = fma(fd, fd, S2);
@@ -149,16 +146,13 @@ __global__ __launch_bounds__(kSampleThreads) void sample_kernel(const SampleArgs
                 const int64_t g = g0 + (int64_t)j * kSampleThreads;
                 const int64_t s0 = 4 * g;
                 if (s0 >= N) break;
+                const int nvalid = (int)min((int64_t)4, N - s0);
                 uint32_t w[4 * D];
+                uint32_t ctr[D];
                 const uint32_t cb = (uint32_t)g * (uint32_t)D;
 #pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    const U4 r = philox4x32_10(cb + (uint32_t)k, c1, c2, c3, k0, k1);
-                    w[4 * k + 0] = r.x;
-                    w[4 * k + 1] = r.y;
-                    w[4 * k + 2] = r.z;
-                    w[4 * k + 3] = r.w;
-                }
+                for (int k = 0; k < D; ++k) ctr[k] = cb + (uint32_t)k;
+                philox4x32_10_lockstep<D>(ctr, c1, c2, c3, k0, k1, w);
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
                     double x[D];
@@ -167,7 +161,7 @@ __global__ __launch_bounds__(kSampleThreads) void sample_kernel(const SampleArgs
 #pragma unroll
                     for (int i = 0; i < D; ++i) x[i] = fma(h24[i], (double)((w[q * D + i] >> 8) | 1u), lo[i]);
                     double f = I::f64(p, x);
-                    f = (s0 + q < N) ? f : 0.0;
+                    f = (q < nvalid) ? f : 0.0;
                     S1 += f;
                     S2 = fma(f, f, S2);
                 }

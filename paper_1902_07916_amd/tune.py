@@ -1,0 +1,103 @@
+"""Autotuner for the sampling kernel's tile shape.
+
+    python -m paper_1902_07916_amd.tune --out tune.json [--dims 2-12] [--integrands genz_osc,...]
+
+For every (integrand, D, eval) bucket it times the sampling + per-cube
+reduction of a fixed list of root cubes (zmc_cube_estimates, N = 16384 points,
+3 trials) for each candidate cap on the 4-point groups a thread takes per
+chunk (the chunk is 4 * 256 * groups points), and writes the fastest as a
+JSON object {"integrand:dim:eval": groups, ...} that zmc_init() reads from
+`tune_path`.  The table depends only on the bucket, never on what else is
+resident, so a request's result stays independent of its batch.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import tempfile
+import time
+
+CANDIDATES = (2, 4, 8, 16, 32)
+
+
+def _parse_dims(s: str):
+    if "-" in s:
+        a, b = s.split("-")
+        return list(range(int(a), int(b) + 1))
+    return [int(v) for v in s.split(",")]
+
+
+def _params(name: str, D: int):
+    if name == "gauss":
+        return [0.3, 1.0] + [0.5] * D
+    if name == "sin_sum":
+        return []
+    if name == "genz_osc":
+        return [0.25] + [2.0] * D
+    if name in ("genz_ppeak", "genz_gauss"):
+        return [2.0] * D + [0.5] * D
+    if name == "genz_cpeak":
+        return [1.0] * D
+    raise ValueError(name)
+
+
+def time_bucket(name: str, D: int, eval_: str, groups: int, n_cubes: int = 4096, reps: int = 3) -> float:
+    """Seconds per sample of the sampling + reduction kernels with the given cap."""
+    import numpy as np
+    import torch
+    from paper_1902_07916_amd import INTEGRANDS, Integrator, make_request
+    key = "%d:%d:%d" % (INTEGRANDS[name], D, 1 if eval_ == "fp32" else 0)
+    with tempfile.NamedTemporaryFile("w", suffix=".json", delete=False) as fh:
+        json.dump({key: groups}, fh)
+        path = fh.name
+    try:
+        zi = Integrator(arena_bytes=2 << 30, tune_path=path)
+        d = 2
+        while d ** D < n_cubes and d < 64:
+            d += 1
+        req = make_request(name, _params(name, D), [0.0] * D, [1.0] * D, d, 16384, 3, 0, 1.0, 1, eval=eval_)
+        n = min(n_cubes, d ** D)
+        uids = np.arange(n, dtype=np.uint64)
+        zi.cube_estimates(req, 0, uids, sums=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            zi.cube_estimates(req, 0, uids, sums=False)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        zi.close()
+        return dt / (n * 3 * 16384)
+    finally:
+        os.unlink(path)
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--dims", default="2-12")
+    ap.add_argument("--integrands", default="genz_osc,genz_ppeak,genz_cpeak,genz_gauss,gauss,sin_sum")
+    ap.add_argument("--evals", default="fp32")
+    a = ap.parse_args(argv)
+    from paper_1902_07916_amd import INTEGRANDS
+    table = {}
+    if os.path.exists(a.out):
+        table = json.load(open(a.out))
+    for name in a.integrands.split(","):
+        for D in _parse_dims(a.dims):
+            for ev in a.evals.split(","):
+                times = {g: time_bucket(name, D, ev, g) for g in CANDIDATES}
+                best = min(times, key=times.get)
+                key = "%d:%d:%d" % (INTEGRANDS[name], D, 1 if ev == "fp32" else 0)
+                table[key] = best
+                print("%-11s D=%2d %s  best groups=%2d  %s" % (name, D, ev, best,
+                      " ".join("%d:%.3gns" % (g, t * 1e9) for g, t in times.items())), flush=True)
+                with open(a.out, "w") as fh:
+                    json.dump(table, fh, indent=1, sort_keys=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    sys.exit(main())

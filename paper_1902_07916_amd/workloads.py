@@ -115,7 +115,7 @@ def serving_stream(rate=200.0, duration=60.0, seed=11, samples=4096, trials=3, m
         fam = GENZ_FAMILIES[int(rng.integers(0, 4))]
         params = _genz_params(fam, rng, D)
         rtol = 10.0 ** rng.uniform(-5.0, -3.0)
-        d = max(dd for dd in range(2, 7) if dd ** D <= max_root_cubes)
+        d = max([1] + [dd for dd in range(2, 7) if dd ** D <= max_root_cubes])
         out.append((t, dict(integrand=fam, params=params, lower=[0.0] * D, upper=[1.0] * D, divisions=d,
                             samples=samples, trials=trials, max_depth=max_depth, sigma_mult=sigma_mult,
                             seed=0, eval=eval, rtol=rtol, max_cubes_per_level=max_cubes_per_level)))

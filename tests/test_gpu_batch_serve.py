@@ -1,0 +1,114 @@
+"""Batched and served integration: every integral of a batch (or of the
+serving mix) gives bitwise the result it gives alone, and agrees with the
+oracle run on that integral alone."""
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from common import oracle_problem, rel, request  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _small_batch(n, eval_="fp32", seed=7):
+    from paper_1902_07916_amd import workloads as W
+    # small enough for the oracle: <= 300 root cubes, 128 points, one
+    # refinement at sigma 1, next level capped at 20000 cubes (truncation)
+    return W.genz_batch(n=n, seed=seed, samples=128, trials=3, max_depth=1, sigma_mult=1.0, eval=eval_,
+                        max_root_cubes=300, max_cubes_per_level=20000)
+
+
+def _same(a, b):
+    return (a.integral == b.integral and a.std == b.std and a.cubes_per_level == b.cubes_per_level
+            and a.selected_per_level == b.selected_per_level and a.flags == b.flags and a.status == b.status)
+
+
+@pytest.fixture(scope="module")
+def zi():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1902_07916_amd import Integrator
+    z = Integrator(arena_bytes=8 << 30, serve=True)
+    yield z
+    z.close()
+
+
+@pytest.mark.parametrize("eval_", ["fp64", "fp32"])
+def test_batch_matches_alone_and_oracle(zi, orc, eval_):
+    ws = _small_batch(24, eval_)
+    reqs = [request(w) for w in ws]
+    batch = zi.integrate_batch(reqs)
+    for w, rq, b in zip(ws, reqs, batch):
+        alone = zi.integrate_request(rq)
+        assert _same(b, alone), (w, b, alone)
+        o = orc.integrate(oracle_problem(orc, w))
+        assert o.status == 0 and b.status == 0
+        tol = 1e-6 if eval_ == "fp64" else 1e-4
+        if [L.n for L in o.levels] == b.cubes_per_level:
+            assert abs(b.integral - o.integral) <= tol * max(abs(o.integral), o.sum_abs), (w, b.integral,
+                                                                                          o.integral)
+        else:
+            # a decision inside the rounding band flipped: the trees may differ,
+            # the estimates must still agree statistically
+            assert eval_ == "fp32"
+            assert abs(b.integral - o.integral) <= 5 * math.hypot(b.stderr, o.stderr)
+
+
+def test_batch_mixed_dims_full_generator(zi):
+    # the batched generator's shape: D uniform in 2..12, four families
+    from paper_1902_07916_amd import workloads as W
+    ws = W.genz_batch(n=64, samples=1024, max_root_cubes=5000)
+    reqs = [request(w) for w in ws]
+    out = zi.integrate_batch(reqs)
+    assert all(r.status == 0 for r in out)
+    for i in (0, 17, 63):
+        assert _same(out[i], zi.integrate_request(reqs[i]))
+
+
+def test_serving_mix_matches_alone(zi, orc):
+    from paper_1902_07916_amd import workloads as W
+    stream = W.serving_stream(rate=400.0, duration=0.1, samples=512, max_root_cubes=2048)
+    reqs = [request(w) for _, w in stream]
+    assert len(reqs) >= 20
+    t0 = time.perf_counter()
+    tickets = []
+    for (t, w), rq in zip(stream, reqs):
+        while time.perf_counter() - t0 < t:
+            time.sleep(0.0005)
+        tickets.append(zi.submit(rq))
+    served = [zi.poll(t, wait=True) for t in tickets]
+    st = zi.serve_stats()
+    assert st["completed"] >= len(reqs) and st["queued"] == 0
+    for (_, w), rq, s in zip(stream, reqs, served):
+        assert s.status == 0
+        alone = zi.integrate_request(rq)
+        assert _same(s, alone)
+        assert s.latency_ms > 0
+    # rtol stop: a met tolerance is a real one
+    for rq, s in zip(reqs, served):
+        if s.flags & 2:
+            assert s.stderr <= (1 + 1e-12) * rq.rtol * abs(s.integral)
+    # and one served request against the oracle
+    w = stream[0][1]
+    o = orc.integrate(oracle_problem(orc, w))
+    assert abs(served[0].integral - o.integral) <= 1e-4 * max(abs(o.integral), o.sum_abs) or \
+        abs(served[0].integral - o.integral) <= 5 * math.hypot(served[0].stderr, o.stderr)
+
+
+def test_serving_cancel_and_errors(zi):
+    from paper_1902_07916_amd import ZmcError, make_request
+    big = make_request("genz_osc", [0.1] + [2.0] * 8, [0.0] * 8, [1.0] * 8, 3, 1 << 16, 3, 4, 5.0, 1, eval="fp32")
+    t = zi.submit(big)
+    zi.cancel(t)
+    r = zi.poll(t, wait=True)
+    assert r.status in (0, -8)
+    with pytest.raises(ZmcError):
+        zi.poll(t)        # collected already
+    with pytest.raises(ZmcError):
+        zi.submit(make_request("gauss", [0.1], [0.0], [1.0], 2, 16, 3, 1, 1.0, 1))  # wrong params

@@ -1,0 +1,153 @@
+"""Parity at the full benchmark sizes, where the oracle cannot run the whole
+tree: every step is checked on what the oracle can compute one by one or on
+properties that hold at any size.
+
+ * sampled cubes of every level: m, s recomputed by the oracle;
+ * threshold: the oracle's threshold over the GPU's own list of s;
+ * selection: the strict rule s > thr against that threshold (bit-exact
+   outside a 1e-12 band, which covers only the threshold's rounding);
+ * next list: the children of the selected parents in order;
+ * totals: the sum of the accepted means / variances of the trace;
+ * the integral against the closed form (statistical) and FP32 vs FP64."""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+import closed_forms as cf  # noqa: E402
+from common import margin_band_ok, oracle_problem, rel  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def zi():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1902_07916_amd import Integrator
+    z = Integrator(arena_bytes=48 << 30)
+    yield z
+    z.close()
+
+
+def _check_levels(orc, w, r, n_sample, m_tol, m_floor=0.0):
+    """m_floor: absolute slack for values FP32 cannot represent (a cube whose
+    FP64 estimate is ~1e-200 reads 0 in FP32)."""
+    p = oracle_problem(orc, w)
+    D = len(w["lower"])
+    rng = np.random.default_rng(0)
+    M = S2 = 0.0
+    acc_m = []
+    acc_s2 = []
+    for l, L in enumerate(r.trace):
+        assert len(L["uid"]) == L["n"] == r.cubes_per_level[l]
+        # sampled cubes recomputed by the oracle
+        idx = np.unique(np.concatenate([[0, L["n"] - 1], rng.integers(0, L["n"], n_sample)]))
+        for i in idx:
+            st, I, m, s, sa = orc.cube(p, l, int(L["uid"][i]))
+            assert st == 0
+            assert abs(L["m"][i] - m) <= m_tol * sa + m_floor, (l, i, L["m"][i], m, sa)
+            assert abs(L["s"][i] - s) <= m_tol * sa * 10 + 1e-9 * s + m_floor, (l, i, L["s"][i], s)
+        if l < w["max_depth"] and l + 1 < len(r.trace):
+            thr, mu, sd = orc.threshold(L["s"], w["sigma_mult"])
+            assert rel(r.thr_per_level[l], thr) < 1e-12
+            band = margin_band_ok(L["s"], L["sel"], thr, 1e-12)
+            assert len(band) == 0, "cubes within 1e-12 of the threshold: %s" % band
+            assert int(L["sel"].sum()) == r.selected_per_level[l]
+            parents = L["uid"][L["sel"].astype(bool)]
+            kids = ((parents[:, None] << np.uint64(D)) | np.arange(2**D, dtype=np.uint64)[None, :]).ravel()
+            assert np.array_equal(r.trace[l + 1]["uid"], kids)
+            for j in rng.integers(0, len(parents), 4):
+                assert np.array_equal(orc.children(int(parents[j]), D), kids[j * 2**D:(j + 1) * 2**D])
+            keep = ~L["sel"].astype(bool)
+        else:
+            keep = np.ones(L["n"], bool)
+        acc_m.append(L["m"][keep])
+        acc_s2.append(L["s"][keep] ** 2)
+    M = math.fsum(np.concatenate(acc_m))
+    S2 = math.fsum(np.concatenate(acc_s2))
+    assert rel(r.integral, M) < 1e-10 or abs(r.integral - M) < 1e-12 * float(np.abs(np.concatenate(acc_m)).sum())
+    assert rel(r.std, math.sqrt(S2)) < 1e-10
+
+
+@pytest.mark.parametrize("eval_,tol", [("fp32", 2e-5), ("fp64", 1e-12)])
+def test_sin6d_full(zi, orc, eval_, tol):
+    from paper_1902_07916_amd import workloads as W
+    w = W.sin6d(eval=eval_)
+    r = zi.integrate(**w, trace=True, trace_capacity=1 << 23)
+    assert r.status == 0 and r.levels_run == 3 and r.flags == 0
+    print("sin6d %s: I=%.9g stderr=%.3g levels=%s selected=%s" % (eval_, r.integral, r.stderr, r.cubes_per_level,
+                                                                 r.selected_per_level))
+    _check_levels(orc, w, r, 12, tol)
+    exact = cf.f1_exact()
+    assert abs(r.integral - exact) <= 5 * r.stderr
+
+
+def _accepted(L, last):
+    keep = np.ones(L["n"], bool) if last else ~L["sel"].astype(bool)
+    return L["uid"][keep], L["m"][keep]
+
+
+def test_sin6d_fp32_vs_fp64(zi):
+    """FP32 evaluation against the FP64 path on the same points.  The
+    difference splits into (i) arithmetic: cubes evaluated and accepted in
+    both runs, and (ii) decisions that flipped within rounding of the
+    threshold, after which the two trees estimate that cube differently.
+    (i) must be within 1e-4 of |I|; (ii) only at cubes whose FP64 margin is
+    below 1e-4."""
+    from paper_1902_07916_amd import workloads as W
+    a = zi.integrate(**W.sin6d(eval="fp32"), trace=True, trace_capacity=1 << 23)
+    b = zi.integrate(**W.sin6d(eval="fp64"), trace=True, trace_capacity=1 << 23)
+    arith = 0.0
+    flips = 0
+    nl = min(a.levels_run, b.levels_run)
+    for l in range(nl):
+        La, Lb = a.trace[l], b.trace[l]
+        last = l == W.sin6d()["max_depth"]
+        common, ia, ib = np.intersect1d(La["uid"], Lb["uid"], assume_unique=True, return_indices=True)
+        V = (10.0 / 6 / 2**l) ** 6
+        assert np.max(np.abs(La["m"][ia] - Lb["m"][ib])) <= 2e-6 * V
+        if not last:
+            fl = La["sel"][ia] != Lb["sel"][ib]
+            flips += int(fl.sum())
+            margin = np.abs(Lb["s"][ib] - b.thr_per_level[l]) / b.thr_per_level[l]
+            assert np.all(margin[fl] < 1e-4), margin[fl]
+            both = ~La["sel"][ia].astype(bool) & ~Lb["sel"][ib].astype(bool)
+        else:
+            both = np.ones(len(ia), bool)
+        arith += float(np.sum(La["m"][ia][both] - Lb["m"][ib][both]))
+    total = a.integral - b.integral
+    print("fp32-fp64: total %.3g, arithmetic %.3g (%.2g of |I|), flips %d" % (total, arith, abs(arith / b.integral),
+                                                                            flips))
+    assert abs(arith) <= 1e-4 * abs(b.integral)
+    if flips == 0:
+        assert rel(a.integral, b.integral) < 1e-4
+
+
+@pytest.mark.parametrize("eval_,tol", [("fp32", 2e-5), ("fp64", 1e-12)])
+def test_gauss9d_full(zi, orc, eval_, tol):
+    from paper_1902_07916_amd import workloads as W
+    w = W.narrow_gauss9d(eval=eval_)
+    r = zi.integrate(**w, trace=True, trace_capacity=1 << 22)
+    assert r.status == 0
+    print("gauss9d %s: I=%.9g stderr=%.3g levels=%s selected=%s" % (eval_, r.integral, r.stderr,
+                                                                   r.cubes_per_level, r.selected_per_level))
+    _check_levels(orc, w, r, 3, tol, m_floor=1e-30 if eval_ == "fp32" else 0.0)
+    # The peak (width 0.02) sits on the common corner of the 512 level-1
+    # children and is hit ~0.17 times per trial, so many cubes see no hit in
+    # all 5 trials and are accepted with m = s = 0: the method underestimates
+    # here (about 0.6 of the exact value) with an optimistic stderr.  The
+    # check is only that the estimate is of the right order.
+    exact = cf.gauss(0.02, 1.0, [0.5] * 9, [0.0] * 9, [1.0] * 9)
+    assert 0.3 * exact < r.integral < 1.5 * exact
+
+
+def test_gauss4d_full_vs_closed_form(zi):
+    from paper_1902_07916_amd import workloads as W
+    r = zi.integrate(**W.gauss4d(eval="fp64"))
+    exact = cf.gauss(0.2, 1.0, [0.0] * 4, [-1.0] * 4, [1.0] * 4)
+    assert abs(r.integral - exact) <= 5 * r.stderr
