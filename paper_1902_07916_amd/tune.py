@@ -73,13 +73,51 @@ def time_bucket(name: str, D: int, eval_: str, groups: int, n_cubes: int = 4096,
         os.unlink(path)
 
 
+def rate_table(evals=("fp32", "fp64"), dims=(2, 4, 6, 9, 12, 16), n_target=65536, N=16384, trials=3):
+    """Sampling-kernel rate per bucket from HIP-event kernel time: one level
+    (max_depth 0) over d^D >= n_target root cubes of [0,1]^D."""
+    import torch
+    from paper_1902_07916_amd import Integrator, make_request
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    zi = Integrator(arena_bytes=16 << 30)
+    rows = []
+    for ev in evals:
+        for name in ("sin_sum", "gauss", "genz_osc", "genz_ppeak", "genz_cpeak", "genz_gauss"):
+            for D in dims:
+                if ev == "fp64" and D not in (4, 6, 9):
+                    continue
+                d = 2
+                while d ** D < n_target:
+                    d += 1
+                req = make_request(name, _params(name, D), [0.0] * D, [1.0] * D, d, N, trials, 0, 1.0, 1, eval=ev)
+                zi.integrate_request(req)
+                torch.cuda.synchronize()
+                rs = [zi.integrate_request(req) for _ in range(3)]
+                ms = min(r.sample_ms_per_level[0] for r in rs)
+                sps = rs[0].n_samples / (ms * 1e-3)
+                slots = bench.valu_slots_per_sample(name, D, ev)["total"]
+                frac = sps * slots / bench.VALU_PEAK
+                rows.append(dict(eval=ev, integrand=name, D=D, cubes=d ** D, samples_per_s=sps, frac=frac))
+                print("%s %-11s D=%2d cubes=%7d %.3e samples/s  %5.1f%% of ALU roofline" % (
+                    ev, name, D, d ** D, sps, 100 * frac), flush=True)
+    zi.close()
+    return rows
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", required=True)
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--table", action="store_true", help="print the sampling rate per bucket and exit")
     ap.add_argument("--dims", default="2-12")
     ap.add_argument("--integrands", default="genz_osc,genz_ppeak,genz_cpeak,genz_gauss,gauss,sin_sum")
     ap.add_argument("--evals", default="fp32")
     a = ap.parse_args(argv)
+    if a.table:
+        rate_table()
+        return 0
+    if not a.out:
+        ap.error("--out is required unless --table")
     from paper_1902_07916_amd import INTEGRANDS
     table = {}
     if os.path.exists(a.out):
