@@ -47,6 +47,7 @@ class Problem(C.Structure):
     _fields_ = [
         ("integrand", C.c_int32), ("dim", C.c_int32), ("divisions", C.c_int32),
         ("trials", C.c_int32), ("max_depth", C.c_int32), ("n_params", C.c_int32),
+        ("split", C.c_int32), ("scope", C.c_int32),
         ("samples", C.c_int64), ("max_cubes_per_level", C.c_int64),
         ("sigma_mult", C.c_double), ("rtol", C.c_double), ("seed", C.c_uint64),
         ("lower", C.c_double * MAX_DIM), ("upper", C.c_double * MAX_DIM),
@@ -77,7 +78,7 @@ def lib():
         L.oracle_uniform.restype = C.c_double
         L.oracle_word.argtypes = [C.c_uint64, C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_int64, C.c_int]
         L.oracle_word.restype = C.c_uint32
-        L.oracle_cube_lattice.argtypes = [C.c_int, C.c_int, C.c_int, C.c_uint64, C.POINTER(C.c_uint64)]
+        L.oracle_cube_lattice.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint64, C.POINTER(C.c_uint64)]
         L.oracle_cube_bounds.argtypes = [P, C.c_int, C.c_uint64, C.POINTER(C.c_double),
                                          C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.oracle_n_params.argtypes = [C.c_int, C.c_int]
@@ -91,7 +92,7 @@ def lib():
         L.oracle_threshold.argtypes = [C.POINTER(C.c_double), C.c_int64, C.c_double,
                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.oracle_threshold.restype = C.c_double
-        L.oracle_children.argtypes = [C.c_uint64, C.c_int, C.POINTER(C.c_uint64)]
+        L.oracle_children.argtypes = [C.c_uint64, C.c_int, C.c_int, C.POINTER(C.c_uint64)]
         L.oracle_validate.argtypes = [P]
         L.oracle_integrate.argtypes = [P, C.POINTER(Replay), C.c_double]
         L.oracle_integrate.restype = C.c_void_p
@@ -108,6 +109,7 @@ def lib():
             f.argtypes = [C.c_void_p, C.c_int]
             f.restype = C.POINTER(t)
         L.oracle_level_stats.argtypes = [C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+        L.oracle_set_user.argtypes = [C.c_int, C.c_void_p, C.c_int]
         if L.oracle_sizeof_problem() != C.sizeof(Problem):
             raise RuntimeError("oracle_problem layout mismatch")
         _lib = L
@@ -115,9 +117,10 @@ def lib():
 
 
 def problem(integrand, dim, lower, upper, divisions, samples, trials, max_depth, sigma_mult, seed,
-            params=(), rtol=0.0, max_cubes_per_level=1 << 24) -> Problem:
+            params=(), rtol=0.0, max_cubes_per_level=1 << 24, split=2, scope=0) -> Problem:
     p = Problem()
     p.integrand, p.dim, p.divisions = int(integrand), int(dim), int(divisions)
+    p.split, p.scope = int(split), int(scope)
     p.trials, p.max_depth, p.n_params = int(trials), int(max_depth), len(params)
     p.samples, p.max_cubes_per_level = int(samples), int(max_cubes_per_level)
     p.sigma_mult, p.rtol, p.seed = float(sigma_mult), float(rtol), int(seed) & ((1 << 64) - 1)
@@ -132,6 +135,39 @@ def problem(integrand, dim, lower, upper, divisions, samples, trials, max_depth,
     for j, v in enumerate(params):
         p.params[j] = float(v)
     return p
+
+
+_user_libs = []
+
+
+def build_user(body: str) -> str:
+    """Compile a user integrand body with g++ into a shared library exposing
+    double zmc_user_f(const double* x, const double* p, int D), the same body
+    the GPU path compiles (there `real` is double or float)."""
+    import hashlib
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    tag = hashlib.sha256(body.encode()).hexdigest()[:16]
+    src = os.path.join(BUILD_DIR, "user_%s.cpp" % tag)
+    so = os.path.join(BUILD_DIR, "user_%s.so" % tag)
+    if not os.path.exists(so):
+        with open(src, "w") as fh:
+            fh.write("#include <cmath>\nusing namespace std;\n"
+                     "extern \"C\" double zmc_user_f(const double* x, const double* p, int D)\n"
+                     "{\n    using real = double;\n    (void)p;\n    (void)D;\n" + body + "\n}\n")
+        tmp = so + ".tmp%d" % os.getpid()
+        subprocess.run(["g++", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o", tmp, src], check=True)
+        os.replace(tmp, so)
+    return so
+
+
+def set_user(integrand_id: int, body: str, n_params: int) -> None:
+    """Register a user integrand with the oracle under the same id the GPU
+    library returned."""
+    lib_u = C.CDLL(build_user(body))
+    _user_libs.append(lib_u)
+    fn = C.cast(lib_u.zmc_user_f, C.c_void_p).value
+    if lib().oracle_set_user(int(integrand_id), fn, int(n_params)) != 0:
+        raise ValueError("oracle_set_user failed")
 
 
 def philox(ctr, key):
@@ -150,9 +186,9 @@ def word(seed, uid, level, trial, dim, s, i) -> int:
     return lib().oracle_word(int(seed), int(uid), int(level), int(trial), int(dim), int(s), int(i))
 
 
-def lattice(dim, divisions, level, uid):
+def lattice(dim, divisions, level, uid, split=2):
     K = (C.c_uint64 * MAX_DIM)()
-    lib().oracle_cube_lattice(dim, divisions, level, int(uid), K)
+    lib().oracle_cube_lattice(dim, divisions, split, level, int(uid), K)
     return np.array(K[:dim], dtype=np.uint64)
 
 
@@ -198,9 +234,9 @@ def threshold(s, sigma_mult):
     return thr, mu.value, sd.value
 
 
-def children(uid, dim):
-    out = (C.c_uint64 * (1 << dim))()
-    lib().oracle_children(int(uid), dim, out)
+def children(uid, dim, split=2):
+    out = (C.c_uint64 * (split ** dim))()
+    lib().oracle_children(int(uid), dim, split, out)
     return np.array(out[:], dtype=np.uint64)
 
 

@@ -21,6 +21,8 @@
  *   oracle_cube_trial     pinned: closed forms (erf, complex exponential, atan,
  *                         inclusion-exclusion, monomials), 2-D Riemann sums.
  *   oracle_threshold      pinned: numpy population std; hand examples.
+ *   oracle_set_user       pinned: a user function equal to a registry
+ *                         integrand reproduces it bit for bit; closed form.
  *   oracle_integrate      pinned: closed forms within k*stderr, constant
  *                         integrand exact, Cantelli bound on selections,
  *                         paper's printed anchors (Tables 1, 2) as loose sanity.
@@ -58,6 +60,12 @@ typedef struct {
     int32_t trials;      /* n1: independent repetitions per sub-domain     */
     int32_t max_depth;   /* refinement rounds after the root division      */
     int32_t n_params;
+    int32_t split;       /* b: a split cuts every axis into b parts (b^D
+                            children); 2 = bisection (default reading), b = d
+                            = the paper's "k equal sub-sub-domains"        */
+    int32_t scope;       /* threshold population: 0 = all cubes of a level
+                            (default reading), 1 = the children of one
+                            parent (roots: all roots)                       */
     int64_t samples;     /* N: points per trial per sub-domain             */
     int64_t max_cubes_per_level;
     double sigma_mult;
@@ -134,20 +142,42 @@ uint32_t oracle_word(uint64_t seed, uint64_t uid, int level, int trial, int dim,
 /* upper/lower half along axis i.                                              */
 /* ------------------------------------------------------------------------- */
 
-/* Integer lattice coordinates of a cube at `level`: cell index along each
- * axis on a grid of d * 2^level cells. */
-void oracle_cube_lattice(int dim, int divisions, int level, uint64_t uid, uint64_t* K)
+static uint64_t ipow_u64(uint64_t b, int e)
 {
-    /* the root index sits above the D*level path bits (none left at 64) */
-    uint64_t root = (dim * level >= 64) ? 0 : (uid >> (uint64_t)(dim * level));
+    uint64_t r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
+
+/* Integer lattice coordinates of a cube at `level`: cell index along each
+ * axis on a grid of d * b^level cells.  uid = root * (b^D)^level + path,
+ * the path holding one base-b^D digit per split, and each digit c holding
+ * the part along axis i as its base-b digit D-1-i (axis 0 most significant).
+ * For b = 2 this is uid' = (uid << D) | c with bit D-1-i of c for axis i. */
+void oracle_cube_lattice(int dim, int divisions, int split, int level, uint64_t uid, uint64_t* K)
+{
+    const uint64_t kids = ipow_u64((uint64_t)split, dim);
+    uint64_t path_scale = 1; /* (b^D)^level; overflows only when it reaches 2^64 */
+    int full = 0;
+    for (int j = 0; j < level; ++j) {
+        if (path_scale > (~0ull) / kids) full = 1;
+        path_scale *= kids;
+    }
+    /* the root index sits above the path digits (none left when they fill 64 bits) */
+    uint64_t root = full ? 0 : uid / path_scale;
     for (int i = dim - 1; i >= 0; --i) {
         K[i] = root % (uint64_t)divisions;
         root /= (uint64_t)divisions;
     }
     for (int j = 1; j <= level; ++j) {
-        uint64_t c = (uid >> (uint64_t)(dim * (level - j))) & ((1ull << dim) - 1ull);
-        for (int i = 0; i < dim; ++i)
-            K[i] = 2u * K[i] + ((c >> (uint64_t)(dim - 1 - i)) & 1u);
+        uint64_t c = uid;
+        for (int t = 0; t < level - j; ++t) c /= kids;
+        c %= kids;
+        for (int i = 0; i < dim; ++i) {
+            uint64_t digit = c;
+            for (int t = 0; t < dim - 1 - i; ++t) digit /= (uint64_t)split;
+            K[i] = (uint64_t)split * K[i] + digit % (uint64_t)split;
+        }
     }
 }
 
@@ -155,11 +185,12 @@ void oracle_cube_lattice(int dim, int divisions, int level, uint64_t uid, uint64
 void oracle_cube_bounds(const oracle_problem* p, int level, uint64_t uid, double* lo, double* h, double* vol)
 {
     uint64_t K[OR_MAX_DIM];
-    oracle_cube_lattice(p->dim, p->divisions, level, uid, K);
+    oracle_cube_lattice(p->dim, p->divisions, p->split, level, uid, K);
+    const double parts = (double)ipow_u64((uint64_t)p->split, level); /* b^level, exact */
     double v = 1.0;
     for (int i = 0; i < p->dim; ++i) {
         double h0 = (p->upper[i] - p->lower[i]) / (double)p->divisions;
-        h[i] = ldexp(h0, -level);
+        h[i] = h0 / parts;
         lo[i] = fma((double)K[i], h[i], p->lower[i]);
         v = v * h[i];
     }
@@ -171,8 +202,32 @@ void oracle_cube_bounds(const oracle_problem* p, int level, uint64_t uid, double
 /* Gaussian f2; the Genz families and the test-only constant / monomial are   */
 /* the registry the workloads draw from.                                       */
 /* ------------------------------------------------------------------------- */
+/* User-defined integrands (the paper's package takes general user
+ * functions, abstract and Sec. 3.3): ids 100.. call a registered function
+ * f(x, params, D). */
+#define OR_USER_BASE 100
+#define OR_MAX_USER 64
+typedef double (*oracle_user_fn)(const double* x, const double* p, int dim);
+static oracle_user_fn g_user_fn[OR_MAX_USER];
+static int g_user_np[OR_MAX_USER];
+
+int oracle_set_user(int id, oracle_user_fn f, int n_params)
+{
+    if (id < OR_USER_BASE || id >= OR_USER_BASE + OR_MAX_USER || !f || n_params < 0 || n_params > OR_MAX_PARAMS)
+        return OR_EINVAL;
+    g_user_fn[id - OR_USER_BASE] = f;
+    g_user_np[id - OR_USER_BASE] = n_params;
+    return OR_OK;
+}
+
+static int is_user(int id)
+{
+    return id >= OR_USER_BASE && id < OR_USER_BASE + OR_MAX_USER && g_user_fn[id - OR_USER_BASE] != NULL;
+}
+
 int oracle_n_params(int id, int dim)
 {
+    if (is_user(id)) return g_user_np[id - OR_USER_BASE];
     switch (id) {
     case OR_GAUSS: return 2 + dim;
     case OR_SIN_SUM: return 0;
@@ -189,6 +244,7 @@ int oracle_n_params(int id, int dim)
 double oracle_f(int id, const double* prm, int dim, const double* x)
 {
     const double two_pi = 6.283185307179586476925286766559;
+    if (is_user(id)) return g_user_fn[id - OR_USER_BASE](x, prm, dim);
     switch (id) {
     case OR_GAUSS: { /* A * exp(-sum (x_i - mu_i)^2 / (2 sigma^2)) */
         double sigma = prm[0], A = prm[1], q = 0.0;
@@ -344,11 +400,11 @@ double oracle_threshold(const double* s, int64_t n, double sigma_mult, double* m
     return mu + sigma_mult * sd;
 }
 
-/* The 2^D children of a cube, in order c = 0 .. 2^D - 1. */
-void oracle_children(uint64_t uid, int dim, uint64_t* out)
+/* The b^D children of a cube, in order c = 0 .. b^D - 1. */
+void oracle_children(uint64_t uid, int dim, int split, uint64_t* out)
 {
-    uint64_t nc = 1ull << dim;
-    for (uint64_t c = 0; c < nc; ++c) out[c] = (uid << (uint64_t)dim) | c;
+    uint64_t nc = ipow_u64((uint64_t)split, dim);
+    for (uint64_t c = 0; c < nc; ++c) out[c] = uid * nc + c;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -357,7 +413,7 @@ void oracle_children(uint64_t uid, int dim, uint64_t* out)
 int oracle_validate(const oracle_problem* p)
 {
     if (p->dim < 1 || p->dim > OR_MAX_DIM) return OR_EINVAL;
-    if (p->integrand < 0 || p->integrand >= OR_N_INTEGRANDS) return OR_EINVAL;
+    if (!is_user(p->integrand) && (p->integrand < 0 || p->integrand >= OR_N_INTEGRANDS)) return OR_EINVAL;
     if (p->n_params != oracle_n_params(p->integrand, p->dim)) return OR_EINVAL;
     /* parameter values are not checked: an integrand that evaluates to a
      * non-finite value fails the run with OR_ENONFINITE instead */
@@ -366,6 +422,16 @@ int oracle_validate(const oracle_problem* p)
             if (!(p->params[j] >= 0.0 && p->params[j] <= 16.0 && p->params[j] == floor(p->params[j])))
                 return OR_EINVAL;
     if (p->divisions < 1) return OR_EINVAL;
+    if (p->split < 2 || p->split > 64) return OR_EINVAL;
+    if (p->scope != 0 && p->scope != 1) return OR_EINVAL;
+    {
+        /* at most 2^24 children per split */
+        uint64_t kids = 1;
+        for (int i = 0; i < p->dim; ++i) {
+            kids *= (uint64_t)p->split;
+            if (kids > (1ull << 24)) return OR_EINVAL;
+        }
+    }
     if (p->samples < 1) return OR_EINVAL;
     if ((uint64_t)p->samples * (uint64_t)p->dim > (1ull << 34)) return OR_EINVAL;
     if (p->trials < 2 || p->trials > 255) return OR_EINVAL;
@@ -390,7 +456,18 @@ int oracle_validate(const oracle_problem* p)
             top >>= 1;
         }
     }
-    if (root_bits + p->dim * p->max_depth > 64) return OR_EINVAL;
+    if (p->split == 2) {
+        if (root_bits + p->dim * p->max_depth > 64) return OR_EINVAL;
+    } else {
+        /* uid < d^D * (b^D)^max_depth must fit 64 bits */
+        uint64_t top = 1;
+        for (int i = 0; i < p->dim; ++i) top *= (uint64_t)p->divisions;
+        for (int l = 0; l < p->max_depth; ++l)
+            for (int i = 0; i < p->dim; ++i) {
+                if (top > (~0ull) / (uint64_t)p->split) return OR_EINVAL;
+                top *= (uint64_t)p->split;
+            }
+    }
     return OR_OK;
 }
 
@@ -400,10 +477,13 @@ int oracle_validate(const oracle_problem* p)
 /* Readings of points the paper leaves open:                                   */
 /*  - level 0 holds the k = d^D root cubes; max_depth counts refinement rounds */
 /*    after it, so the paper's "partition depth" is max_depth + 1;             */
-/*  - a selected cube is split into 2^D children (every axis bisected), and    */
-/*    the children replace it (its own mean and std are dropped);              */
+/*  - a selected cube is split into 2^D children (every axis bisected; with  */
+/*    split = b, b^D children, b = d being the paper's "k equal             */
+/*    sub-sub-domains"), and the children replace it (its own mean and std  */
+/*    are dropped);                                                          */
 /*  - the threshold is recomputed over each new list of sub-domains, i.e. per */
-/*    level over all of that level's cubes;                                    */
+/*    level over all of that level's cubes (scope 1: over the children of   */
+/*    each parent);                                                          */
 /*  - selection is the strict "s > thr"; at level max_depth every cube is      */
 /*    accepted;                                                                */
 /*  - result = sum of accepted means; std = sqrt(sum of accepted s^2);         */
@@ -525,14 +605,19 @@ oracle_run* oracle_integrate(const oracle_problem* p, const oracle_replay* rp, d
         r->n_cubes += (uint64_t)n;
         if (r->status != OR_OK) return r;
 
-        /* threshold over this level's list and selection */
+        /* threshold over this level's list (or over each parent's children)
+         * and selection */
         L->min_margin = INFINITY;
         if (level < p->max_depth) {
+            const int64_t group = (p->scope == 1 && level > 0) ? (int64_t)ipow_u64((uint64_t)p->split, D) : n;
             L->thr = oracle_threshold(L->s, n, p->sigma_mult, &L->mu, &L->sd);
+            if (group != n) L->thr = L->mu = L->sd = NAN; /* no single threshold */
+            double thr = 0.0;
             for (int64_t c = 0; c < n; ++c) {
-                int sel = L->s[c] > L->thr;
-                if (L->thr > 0.0) {
-                    double margin = fabs(L->s[c] - L->thr) / L->thr;
+                if (c % group == 0) thr = oracle_threshold(&L->s[c], group, p->sigma_mult, NULL, NULL);
+                int sel = L->s[c] > thr;
+                if (thr > 0.0) {
+                    double margin = fabs(L->s[c] - thr) / thr;
                     if (margin < L->min_margin) L->min_margin = margin;
                     if (margin <= band_eps) {
                         int dec;
@@ -576,7 +661,8 @@ oracle_run* oracle_integrate(const oracle_problem* p, const oracle_replay* rp, d
                 r->flags |= OR_F_RTOL_MET;
             }
         }
-        uint64_t n_next = (uint64_t)L->n_sel << (uint64_t)D;
+        const uint64_t kids = ipow_u64((uint64_t)p->split, D);
+        uint64_t n_next = (uint64_t)L->n_sel * kids;
         if (!stop && n_next > (uint64_t)p->max_cubes_per_level) {
             stop = 1;
             r->flags |= OR_F_TRUNCATED;
@@ -597,8 +683,8 @@ oracle_run* oracle_integrate(const oracle_problem* p, const oracle_replay* rp, d
         int64_t w = 0;
         for (int64_t c = 0; c < n; ++c)
             if (L->sel[c]) {
-                oracle_children(list[c], D, &next[w]);
-                w += (int64_t)1 << D;
+                oracle_children(list[c], D, p->split, &next[w]);
+                w += (int64_t)kids;
             }
         list = next;
         n = (int64_t)n_next;

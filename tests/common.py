@@ -7,7 +7,8 @@ def oracle_problem(orc, w):
     D = len(w["lower"])
     return orc.problem(w["integrand"], D, w["lower"], w["upper"], w["divisions"], w["samples"], w["trials"],
                        w["max_depth"], w["sigma_mult"], w["seed"], params=w["params"], rtol=w.get("rtol", 0.0),
-                       max_cubes_per_level=w.get("max_cubes_per_level", 0) or (1 << 24))
+                       max_cubes_per_level=w.get("max_cubes_per_level", 0) or (1 << 24),
+                       split=w.get("split", 0) or 2, scope=w.get("scope", 0))
 
 
 def request(w):
