@@ -198,13 +198,49 @@ def run_serve(a) -> dict:
             "levels_stepped": st["levels"]}
 
 
+# The paper's own timings on its hardware (Tables 1-4), seconds per run.
+PAPER_TIMES = {"f1_tf": (355.8, "1 x K40m"), "f1_numba": (313.5, "1 x K40m"), "f1_ray": (38.7, "1 x V100"),
+               "f2_numba": (69.7, "1 x K40m"), "f2_ray": (4.8, "1 x V100")}
+
+
+def run_paper(a) -> dict:
+    """The paper's parameter sets on this GPU, 10 seeds each (the paper
+    averages 10 independent runs): mean result, spread, time per run."""
+    import statistics
+
+    import torch
+    from paper_1902_07916_amd import Integrator, workloads
+    zi = Integrator(arena_bytes=int(a.arena_gib * (1 << 30)))
+    out = {}
+    for name in workloads.PAPER_RUNS:
+        w = workloads.paper_run(name, eval="fp32", seed=1)
+        zi.integrate(**w)
+        torch.cuda.synchronize()
+        res, times = [], []
+        for seed in range(1, 11):
+            w = workloads.paper_run(name, eval="fp32", seed=seed)
+            t0 = time.perf_counter()
+            r = zi.integrate(**w)
+            times.append(time.perf_counter() - t0)
+            res.append(r)
+        vals = [r.integral for r in res]
+        out[name] = {"setting": workloads.PAPER_RUNS[name]["ref"], "mean": statistics.mean(vals),
+                     "spread": statistics.pstdev(vals), "mean_stderr": statistics.mean(r.stderr for r in res),
+                     "s_per_run": statistics.mean(times), "samples_per_run": res[0].n_samples,
+                     "samples_per_s": statistics.mean(r.n_samples for r in res) / statistics.mean(times),
+                     "levels": res[0].cubes_per_level,
+                     "paper_s_per_run": PAPER_TIMES[name][0], "paper_hw": PAPER_TIMES[name][1]}
+    zi.close()
+    return out
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sin6d", choices=sorted(WORKLOADS))
-    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve"])
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "paper"])
     ap.add_argument("--no-fp64", action="store_true", help="skip timing the plain FP64 path")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--arena-gib", type=float, default=48.0)
@@ -227,6 +263,9 @@ def main(argv=None) -> int:
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
+    if a.mode == "paper":
+        print(json.dumps({"mode": "paper", **run_paper(a)}))
+        return 0
     if a.mode == "batch":
         print(json.dumps({"mode": "batch", **run_batch(a)}))
         return 0

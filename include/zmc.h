@@ -133,6 +133,13 @@ typedef struct {
     int32_t max_depth;           /* refinement rounds after level 0, 0..15       */
     int32_t eval;                /* zmc_eval                                     */
     int32_t n_params;
+    int32_t split;               /* 0 or 2: a split bisects every axis (2^D
+                                    children); b in 3..64: b parts per axis (b^D
+                                    children, at most 2^24; b = d is the paper's
+                                    "k equal sub-sub-domains", Sec. 2.1)         */
+    int32_t threshold_scope;     /* 0: one threshold per level over all its cubes;
+                                    1: one per parent, over its children (the
+                                    roots share one)                             */
     int32_t reserved;
     int64_t samples_per_cube;    /* N >= 1 points per trial, N * D <= 2^34       */
     int64_t max_cubes_per_level; /* 0 = default (2^24)                           */
@@ -193,8 +200,9 @@ int zmc_shutdown(void);
  * EINVAL when: dim not in 1..16; lower_i >= upper_i or not finite; d < 1;
  * N < 1 or N*D > 2^34; trials not in 2..255; max_depth not in 0..15;
  * sigma_mult < 0 or not finite; unknown integrand or wrong n_params; a
- * MONOMIAL exponent outside 0..16 or not an integer; ceil(log2(d^D)) +
- * D*max_depth > 64 (uid overflow); d^D > max_cubes_per_level.
+ * MONOMIAL exponent outside 0..16 or not an integer; d^D * (b^D)^max_depth
+ * > 2^64 (uid overflow; b = 2 unless the request sets split); d^D >
+ * max_cubes_per_level; split or threshold_scope out of range.
  * ENOMEM when a level does not fit the arena. */
 int zmc_integrate(int integrand_id, const double* params, int n_params, int dim, const double* lower,
                   const double* upper, int divisions_per_axis, int64_t samples_per_cube, int trials,
@@ -250,6 +258,21 @@ int zmc_debug_points(const zmc_request* req, int level, uint64_t uid, int trial,
  * S1[n*trials], S2[n*trials] (host arrays). */
 int zmc_cube_estimates(const zmc_request* req, int level, const uint64_t* uids, int64_t n, double* m,
                        double* s, double* S1, double* S2, void* stream);
+
+/* User-defined integrand (the paper's package integrates general user
+ * functions, abstract and Sec. 3.3): `body` is the body of
+ *     template <typename real> real f(const real* x, const double* p)
+ * in C++ device syntax, where x[0..D-1] is the point (`real` is double in
+ * ZMC_EVAL_FP64 and float in ZMC_EVAL_FP32, with absolute coordinates), p
+ * holds the request's n_params params and `D` is a compile-time constant,
+ * e.g. "real t = 0; for (int i = 0; i < D; ++i) t += x[i]; return sin(t);".
+ * The body is compiled with hipRTC for gfx950 now (to report errors) and once
+ * per (D, eval) on first use; the returned id (>= 100) is then used as
+ * integrand_id / zmc_request.integrand with n_params params.  Does not need
+ * zmc_init().  EINVAL: NULL arguments, n_params outside 0..34, a body that
+ * does not compile (zmc_strerror(ZMC_EINVAL) holds the compiler log), or more
+ * than 64 registrations. */
+int zmc_register_integrand(const char* body, int n_params, int* integrand_id);
 
 /* Text for a status code, or the last HIP error text for ZMC_EDEVICE. */
 const char* zmc_strerror(int status);

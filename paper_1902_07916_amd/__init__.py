@@ -24,7 +24,7 @@ from . import _abi
 from ._abi import (CONST, EVAL_FP32, EVAL_FP64, F_RTOL_MET, F_TRUNCATED, GAUSS, GENZ_CPEAK, GENZ_GAUSS,
                    GENZ_OSC, GENZ_PPEAK, INTEGRANDS, MONOMIAL, SIN_SUM, ZmcError, check)
 
-__all__ = ["Integrator", "Result", "make_request", "ZmcError", "INTEGRANDS", "GAUSS", "SIN_SUM", "GENZ_OSC",
+__all__ = ["Integrator", "Result", "make_request", "register_integrand", "ZmcError", "INTEGRANDS", "GAUSS", "SIN_SUM", "GENZ_OSC",
            "GENZ_PPEAK", "GENZ_CPEAK", "GENZ_GAUSS", "CONST", "MONOMIAL", "EVAL_FP64", "EVAL_FP32",
            "F_TRUNCATED", "F_RTOL_MET"]
 
@@ -42,8 +42,10 @@ def _eval_id(x) -> int:
 
 
 def make_request(integrand, params, lower, upper, divisions, samples, trials, max_depth, sigma_mult, seed,
-                 eval="fp64", rtol=0.0, max_cubes_per_level=0) -> _abi.Request:
-    """Fill a zmc_request; lower/upper may be scalars (broadcast to dim)."""
+                 eval="fp64", rtol=0.0, max_cubes_per_level=0, split=0, threshold_scope=0) -> _abi.Request:
+    """Fill a zmc_request; lower/upper may be scalars (broadcast to dim).
+    split: parts per axis of a split (0/2 = bisection); threshold_scope: 0 per
+    level, 1 per parent."""
     params = [float(v) for v in params]
     lower = np.atleast_1d(np.asarray(lower, dtype=np.float64))
     upper = np.atleast_1d(np.asarray(upper, dtype=np.float64))
@@ -60,6 +62,8 @@ def make_request(integrand, params, lower, upper, divisions, samples, trials, ma
     r.n_params = len(params)
     r.samples_per_cube = int(samples)
     r.max_cubes_per_level = int(max_cubes_per_level)
+    r.split = int(split)
+    r.threshold_scope = int(threshold_scope)
     r.sigma_mult = float(sigma_mult)
     r.rtol = float(rtol)
     r.seed = int(seed) & ((1 << 64) - 1)
@@ -75,12 +79,23 @@ def make_request(integrand, params, lower, upper, divisions, samples, trials, ma
     return r
 
 
+def register_integrand(body: str, n_params: int = 0) -> int:
+    """Compile a user integrand (see zmc_register_integrand in zmc.h) and
+    return its id, usable wherever an integrand id or name is accepted.
+    Raises ZmcError (EINVAL, with the compiler log) if it does not compile."""
+    L = _abi.load()
+    out = C.c_int()
+    check(L.zmc_register_integrand(body.encode(), int(n_params), C.byref(out)), "zmc_register_integrand")
+    return out.value
+
+
 def request_from_dict(d: dict) -> _abi.Request:
     keys = ("integrand", "params", "lower", "upper", "divisions", "samples", "trials", "max_depth",
             "sigma_mult", "seed")
     kw = {k: d[k] for k in keys}
     return make_request(**kw, eval=d.get("eval", "fp64"), rtol=d.get("rtol", 0.0),
-                        max_cubes_per_level=d.get("max_cubes_per_level", 0))
+                        max_cubes_per_level=d.get("max_cubes_per_level", 0), split=d.get("split", 0),
+                        threshold_scope=d.get("scope", 0))
 
 
 @dataclass
@@ -168,10 +183,10 @@ class Integrator:
 
     # -- synchronous integration ----------------------------------------------
     def integrate(self, integrand, params, lower, upper, divisions, samples, trials, max_depth, sigma_mult, seed,
-                  eval="fp64", rtol=0.0, max_cubes_per_level=0, trace: bool = False,
+                  eval="fp64", rtol=0.0, max_cubes_per_level=0, split=0, scope=0, trace: bool = False,
                   trace_capacity: int = 1 << 20, raise_on_error: bool = True) -> Result:
         req = make_request(integrand, params, lower, upper, divisions, samples, trials, max_depth, sigma_mult,
-                           seed, eval, rtol, max_cubes_per_level)
+                           seed, eval, rtol, max_cubes_per_level, split, scope)
         return self.integrate_request(req, trace=trace, trace_capacity=trace_capacity,
                                       raise_on_error=raise_on_error)
 

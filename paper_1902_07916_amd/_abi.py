@@ -28,7 +28,7 @@ F_TRUNCATED, F_RTOL_MET = 1, 2
 
 EXPORTS = ("zmc_init", "zmc_shutdown", "zmc_integrate", "zmc_integrate_request", "zmc_integrate_batch",
            "zmc_submit", "zmc_poll", "zmc_cancel", "zmc_serve_stats", "zmc_debug_philox", "zmc_debug_points",
-           "zmc_cube_estimates", "zmc_strerror", "zmc_version", "zmc_struct_size")
+           "zmc_cube_estimates", "zmc_strerror", "zmc_version", "zmc_struct_size", "zmc_register_integrand")
 
 
 class Result(C.Structure):
@@ -47,6 +47,7 @@ class Request(C.Structure):
     _fields_ = [
         ("integrand", C.c_int32), ("dim", C.c_int32), ("divisions_per_axis", C.c_int32),
         ("trials", C.c_int32), ("max_depth", C.c_int32), ("eval", C.c_int32), ("n_params", C.c_int32),
+        ("split", C.c_int32), ("threshold_scope", C.c_int32),
         ("reserved", C.c_int32), ("samples_per_cube", C.c_int64), ("max_cubes_per_level", C.c_int64),
         ("sigma_mult", C.c_double), ("rtol", C.c_double), ("seed", C.c_uint64),
         ("lower", C.c_double * MAX_DIM), ("upper", C.c_double * MAX_DIM), ("params", C.c_double * MAX_PARAMS),
@@ -103,6 +104,7 @@ def load(path: str = LIB_PATH):
     L.zmc_version.argtypes = []
     L.zmc_version.restype = C.c_char_p
     L.zmc_struct_size.argtypes = [i32]
+    L.zmc_register_integrand.argtypes = [C.c_char_p, i32, C.POINTER(C.c_int)]
     for i, T in enumerate((Result, Request, Config, Trace)):
         if L.zmc_struct_size(i) != C.sizeof(T):
             raise RuntimeError("ABI mismatch for %s: C %d vs ctypes %d" % (T.__name__, L.zmc_struct_size(i),

@@ -16,6 +16,7 @@
 
 #include "zmc.h"
 #include "zmc_engine.hpp"
+#include "zmc_rtc.hpp"
 
 using namespace zmc;
 
@@ -90,14 +91,30 @@ int fail(int code, const char* msg)
 int validate(const zmc_request& r)
 {
     if (r.dim < 1 || r.dim > ZMC_MAX_DIM) return fail(ZMC_EINVAL, "dim must be in 1..16");
-    if (r.integrand < 0 || r.integrand > ZMC_MONOMIAL) return fail(ZMC_EINVAL, "unknown integrand");
-    if (r.n_params != n_params_of(r.integrand, r.dim)) return fail(ZMC_EINVAL, "wrong number of params");
+    if (r.integrand >= kUserBase) {
+        const int np = rtc_n_params(r.integrand);
+        if (np < 0) return fail(ZMC_EINVAL, "unknown integrand");
+        if (r.n_params != np) return fail(ZMC_EINVAL, "wrong number of params");
+    } else {
+        if (r.integrand < 0 || r.integrand > ZMC_MONOMIAL) return fail(ZMC_EINVAL, "unknown integrand");
+        if (r.n_params != n_params_of(r.integrand, r.dim)) return fail(ZMC_EINVAL, "wrong number of params");
+    }
     if (r.integrand == ZMC_MONOMIAL)
         for (int j = 0; j < r.n_params; ++j)
             if (!(r.params[j] >= 0.0 && r.params[j] <= 16.0 && r.params[j] == floor(r.params[j])))
                 return fail(ZMC_EINVAL, "monomial exponents must be integers in 0..16");
     if (r.eval != ZMC_EVAL_FP64 && r.eval != ZMC_EVAL_FP32) return fail(ZMC_EINVAL, "unknown eval mode");
     if (r.divisions_per_axis < 1) return fail(ZMC_EINVAL, "divisions_per_axis must be >= 1");
+    if (r.split != 0 && (r.split < 2 || r.split > 64)) return fail(ZMC_EINVAL, "split must be 0 (= 2) or in 2..64");
+    if (r.threshold_scope != 0 && r.threshold_scope != 1) return fail(ZMC_EINVAL, "threshold_scope must be 0 or 1");
+    const uint64_t b = r.split ? (uint64_t)r.split : 2u;
+    {
+        uint64_t kids = 1;
+        for (int i = 0; i < r.dim; ++i) {
+            kids *= b;
+            if (kids > (1ull << 24)) return fail(ZMC_EINVAL, "split^dim must be <= 2^24");
+        }
+    }
     if (r.samples_per_cube < 1) return fail(ZMC_EINVAL, "samples_per_cube must be >= 1");
     if ((uint64_t)r.samples_per_cube * (uint64_t)r.dim > (1ull << 34))
         return fail(ZMC_EINVAL, "samples_per_cube * dim must be <= 2^34");
@@ -114,7 +131,17 @@ int validate(const zmc_request& r)
     if (ovf) return fail(ZMC_EINVAL, "d^D overflows 64 bits");
     int root_bits = 0;
     for (uint64_t t = k - 1; t; t >>= 1) ++root_bits;
-    if (root_bits + r.dim * r.max_depth > 64) return fail(ZMC_EINVAL, "uid would overflow 64 bits");
+    if (b == 2) {
+        if (root_bits + r.dim * r.max_depth > 64) return fail(ZMC_EINVAL, "uid would overflow 64 bits");
+    } else {
+        // uid < d^D * (b^D)^max_depth
+        uint64_t top = k;
+        for (int l = 0; l < r.max_depth; ++l)
+            for (int i = 0; i < r.dim; ++i) {
+                if (top > UINT64_MAX / b) return fail(ZMC_EINVAL, "uid would overflow 64 bits");
+                top *= b;
+            }
+    }
     const int64_t cap = r.max_cubes_per_level > 0 ? r.max_cubes_per_level : ZMC_DEFAULT_MAX_CUBES;
     if (k > (uint64_t)cap) return fail(ZMC_EINVAL, "d^D exceeds max_cubes_per_level");
     return ZMC_OK;
@@ -479,6 +506,11 @@ const char* zmc_strerror(int status)
 }
 
 const char* zmc_version(void) { return "zmc-mi355x 0.1 (gfx950)"; }
+
+int zmc_register_integrand(const char* body, int n_params, int* integrand_id)
+{
+    return rtc_register(body, n_params, integrand_id);
+}
 
 int zmc_struct_size(int which)
 {

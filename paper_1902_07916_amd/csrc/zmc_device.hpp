@@ -32,7 +32,10 @@ struct alignas(16) SlotDesc {
     int64_t samples, max_cubes;
     double sigma_mult, rtol;
     uint64_t seed;
-    int64_t reserved;
+    int32_t split;  // parts per axis of a split (2 = bisection)
+    int32_t kids;   // split^dim children per split
+    int32_t scope;  // 0: threshold per level; 1: per parent
+    int32_t reserved;
     double lower[kMaxDim];
     double h0[kMaxDim]; // (upper - lower) / d, the root edge lengths
     double params[kMaxParams];
@@ -48,6 +51,9 @@ struct alignas(16) Segment {
     int64_t child_base; // where its children start in the next list
     int32_t do_split;   // 1: spawn its selected cubes' children
     int32_t need_thr;   // 1: a threshold is formed at this level
+    int64_t group_base; // per-parent thresholds: index of its first sibling group
+    int32_t group_size; // per-parent thresholds: cubes per sibling group (0: one threshold)
+    int32_t pad;
 };
 
 // Sampling work of one (integrand, D, eval) bucket: segment `seg` owns the
@@ -68,6 +74,20 @@ struct alignas(16) TileRec {
 };
 
 enum Decision : int32_t { kSplit = 0, kDone = 1, kTruncated = 2, kRtolMet = 3 };
+
+// Arguments of one sampling launch (one (integrand, D, eval) bucket).
+constexpr int kSampleThreads = 256;
+
+struct SampleArgs {
+    const SlotDesc* slots;
+    const Segment* segs;
+    const BSeg* bsegs;
+    int32_t n_bsegs;
+    int32_t pad;
+    int64_t total_units;
+    const uint64_t* uid;
+    double2* partial;
+};
 
 // Per-segment outcome of one level, read back by the host after every level.
 struct alignas(16) SegStats {
@@ -170,44 +190,65 @@ __device__ __forceinline__ float unit_interval_f32(uint32_t w)
 }
 
 // ---------------------------------------------------------------------------
-// Geometry of cube (uid, level): lattice cell K_i on a grid of d*2^level
-// cells per axis.  Root index r = uid >> (D*level) in row-major order with
-// axis 0 most significant; each refinement appends D bits, bit (D-1-i)
-// choosing the upper half of axis i.
+// Geometry of cube (uid, level): lattice cell K_i on a grid of d*b^level
+// cells per axis.  uid = root * (b^D)^level + path, one base-b^D digit per
+// split, axis 0 the most significant base-b digit of each; for b = 2 this is
+// uid' = (uid << D) | c with bit (D-1-i) of c choosing the upper half of
+// axis i.  Edge lengths h = h0 / b^level (exact for b = 2).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ double level_parts(int split, int level)
+{
+    uint64_t p = 1;
+    for (int j = 0; j < level; ++j) p *= (uint64_t)split;
+    return (double)p;
+}
+
 __device__ __forceinline__ void cube_corner(const SlotDesc& sd, int D, int level, uint64_t uid, double* lo,
                                             double* h)
 {
     uint64_t K[kMaxDim];
-    uint64_t root = (D * level >= 64) ? 0 : (uid >> (uint64_t)(D * level));
     const uint64_t d = (uint64_t)sd.divisions;
-    if (root < (1ull << 32)) {
-        uint32_t r32 = (uint32_t)root;
-        for (int i = D - 1; i >= 0; --i) {
-            K[i] = r32 % (uint32_t)d;
-            r32 /= (uint32_t)d;
-        }
+    const uint64_t b = (uint64_t)sd.split;
+    const uint64_t kids = (uint64_t)sd.kids;
+    uint64_t root;
+    if (b == 2) {
+        root = (D * level >= 64) ? 0 : (uid >> (uint64_t)(D * level));
     } else {
-        for (int i = D - 1; i >= 0; --i) {
-            K[i] = root % d;
-            root /= d;
+        root = uid;
+        for (int j = 0; j < level; ++j) root /= kids;
+    }
+    for (int i = D - 1; i >= 0; --i) {
+        K[i] = root % d;
+        root /= d;
+    }
+    for (int j = 1; j <= level; ++j) {
+        uint64_t c = uid;
+        if (b == 2) {
+            c = uid >> (uint64_t)(D * (level - j));
+            for (int i = 0; i < D; ++i) K[i] = 2u * K[i] + ((c >> (uint64_t)(D - 1 - i)) & 1u);
+        } else {
+            for (int t = 0; t < level - j; ++t) c /= kids;
+            c %= kids;
+            uint64_t digits[kMaxDim];
+            for (int i = D - 1; i >= 0; --i) {
+                digits[i] = c % b;
+                c /= b;
+            }
+            for (int i = 0; i < D; ++i) K[i] = b * K[i] + digits[i];
         }
     }
-    const uint64_t mask = (1ull << D) - 1ull;
-    for (int j = 1; j <= level; ++j) {
-        const uint64_t c = (uid >> (uint64_t)(D * (level - j))) & mask;
-        for (int i = 0; i < D; ++i) K[i] = 2u * K[i] + ((c >> (uint64_t)(D - 1 - i)) & 1u);
-    }
+    const double parts = level_parts(sd.split, level);
     for (int i = 0; i < D; ++i) {
-        h[i] = ldexp(sd.h0[i], -level);
+        h[i] = sd.h0[i] / parts;
         lo[i] = fma((double)K[i], h[i], sd.lower[i]);
     }
 }
 
 __device__ __forceinline__ double cube_volume(const SlotDesc& sd, int D, int level)
 {
+    const double parts = level_parts(sd.split, level);
     double v = 1.0;
-    for (int i = 0; i < D; ++i) v = v * ldexp(sd.h0[i], -level);
+    for (int i = 0; i < D; ++i) v = v * (sd.h0[i] / parts);
     return v;
 }
 

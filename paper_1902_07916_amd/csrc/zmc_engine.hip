@@ -3,6 +3,7 @@
 // integral, applies the stop rules of the tree search (ZMCintegral, Sec. 2.1)
 // and builds the next level's list.
 #include "zmc_engine.hpp"
+#include "zmc_rtc.hpp"
 
 #include <float.h>
 #include <math.h>
@@ -32,6 +33,12 @@ uint64_t ipow_u64(uint64_t b, int e)
 }
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// parts per axis when a cube is split (0 in a request means bisection)
+int split_of(const zmc_request& r) { return r.split ? r.split : 2; }
+
+// children of a split cube: split^D
+int64_t kids_of(const zmc_request& r) { return (int64_t)ipow_u64((uint64_t)split_of(r), r.dim); }
 } // namespace
 
 void set_error(const std::string& s) { g_err = s; }
@@ -51,7 +58,7 @@ TileTable::TileTable()
 {
     for (int f = 0; f < 8; ++f)
         for (int d = 0; d <= ZMC_MAX_DIM; ++d)
-            for (int e = 0; e < 2; ++e) groups[f][d][e] = 16;
+            for (int e = 0; e < 2; ++e) groups[f][d][e] = kDefaultGroups;
 }
 
 // Tuning file: a JSON object whose keys "integrand:dim:eval" map to the
@@ -138,18 +145,18 @@ void Engine::teardown()
     cap_cache_.clear();
 }
 
-// Chunk of one sampling unit: 4 * 256 * groups points, with groups the
-// smaller of the tile table's cap for the bucket and what N needs, so a
+// Chunk of one sampling unit (one wave): 4 * 64 * groups points, with groups
+// the smaller of the tile table's cap for the bucket and what N needs, so a
 // request's chunking depends only on its own parameters.
 int Engine::groups_of(const zmc_request& r) const
 {
-    const int64_t need = ceil_div(r.samples_per_cube, 4LL * kSampleThreads);
+    const int64_t need = ceil_div(r.samples_per_cube, 4LL * 64);
     return (int)std::max<int64_t>(1, std::min<int64_t>(need, tiles_->get(r.integrand, r.dim, r.eval)));
 }
 
 int Engine::nch_of(const zmc_request& r) const
 {
-    const int64_t chunk = 4LL * kSampleThreads * groups_of(r);
+    const int64_t chunk = 4LL * 64 * groups_of(r);
     return (int)ceil_div(r.samples_per_cube, chunk);
 }
 
@@ -184,6 +191,9 @@ int Engine::fill_slot_desc(int slot, const zmc_request& r, hipStream_t st)
     d.sigma_mult = r.sigma_mult;
     d.rtol = r.rtol;
     d.seed = r.seed;
+    d.split = split_of(r);
+    d.kids = (int32_t)kids_of(r);
+    d.scope = r.threshold_scope;
     for (int i = 0; i < r.dim; ++i) {
         d.lower[i] = r.lower[i];
         d.h0[i] = (r.upper[i] - r.lower[i]) / (double)r.divisions_per_axis;
@@ -206,7 +216,7 @@ size_t Engine::reservation_bytes(const zmc_request& r) const
         const double frac = r.sigma_mult > 0 ? 1.0 / (1.0 + r.sigma_mult * r.sigma_mult) : 1.0;
         int64_t nsel = (int64_t)floor((double)n * frac);
         if (r.sigma_mult == 0.0) nsel = n - 1;
-        int64_t nn = nsel << r.dim;
+        int64_t nn = nsel * kids_of(r);
         if (nn > cap || nn < 0) nn = cap;
         worst_next = std::max(worst_next, nn);
         worst = std::max(worst, nn);
@@ -262,7 +272,7 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
                  zmc_trace* trace, bool stats_only, bool want_sums)
 {
     const int ns = (int)live.size();
-    int64_t cube = 0, part = 0, tile = 0;
+    int64_t cube = 0, part = 0, tile = 0, groups = 0;
     bool any_thr = false;
     for (int i = 0; i < ns; ++i) {
         HostSlot& hs = slots_[live[i].slot];
@@ -279,6 +289,15 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
         g.n_tiles = ceil_div(n, kTileCubes);
         g.need_thr = (!stats_only && hs.level < r.max_depth) ? 1 : 0;
         any_thr |= g.need_thr != 0;
+        // per-parent thresholds: below the roots, the list holds whole groups
+        // of siblings in spawn order; a single group is the level itself
+        const int64_t kids = kids_of(r);
+        g.group_base = groups;
+        g.group_size = 0;
+        if (g.need_thr && r.threshold_scope == 1 && hs.level > 0 && n > kids) {
+            g.group_size = (int32_t)kids;
+            groups += n / kids;
+        }
         h_prev_[i] = make_double2(hs.totM, hs.totS2);
         cube += n;
         part += n * (int64_t)r.trials * nch_of(r);
@@ -292,6 +311,7 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
     cur_s_ = (double*)arena_.alloc(cur_side, (size_t)cube * sizeof(double));
     cur_sel_ = (uint8_t*)arena_.alloc(cur_side, (size_t)cube);
     cur_tiles_ = (TileRec*)arena_.alloc(cur_side, (size_t)tile * sizeof(TileRec));
+    double* gthr = groups ? (double*)arena_.alloc(cur_side, (size_t)groups * sizeof(double)) : nullptr;
     cur_S1_ = cur_S2_ = nullptr;
     // per-(cube, trial) sums are only kept for a single integral (trace,
     // cube estimates), where every cube has the same number of trials
@@ -302,7 +322,8 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
         cur_S1_ = (double*)arena_.alloc(cur_side, (size_t)n_trial_entries * sizeof(double));
         cur_S2_ = (double*)arena_.alloc(cur_side, (size_t)n_trial_entries * sizeof(double));
     }
-    if (!partial || !cur_m_ || !cur_s_ || !cur_sel_ || !cur_tiles_ || (sums && (!cur_S1_ || !cur_S2_))) {
+    if (!partial || !cur_m_ || !cur_s_ || !cur_sel_ || !cur_tiles_ || (sums && (!cur_S1_ || !cur_S2_)) ||
+        (groups && !gthr)) {
         set_error("arena exhausted");
         return ZMC_ENOMEM;
     }
@@ -355,9 +376,14 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
         a.total_units = L.units;
         a.uid = cur_uid;
         a.partial = partial;
-        const int64_t cap = capacity(L.integrand, L.dim, L.eval);
-        const int grid = (int)std::min<int64_t>(L.units, cap);
-        ZMC_HIP(launch_sample(L.integrand, L.dim, L.eval, grid, st, a));
+        if (L.integrand >= kUserBase) {
+            const int rc = rtc_launch(L.integrand, L.dim, L.eval, L.units, st, a);
+            if (rc != ZMC_OK) return rc;
+        } else {
+            const int64_t cap = capacity(L.integrand, L.dim, L.eval);
+            const int grid = (int)std::min<int64_t>(L.units, cap);
+            ZMC_HIP(launch_sample(L.integrand, L.dim, L.eval, grid, st, a));
+        }
         ++n_launch;
     }
     ZMC_HIP(hipEventRecord(ev_sample1_, st));
@@ -378,9 +404,12 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
     la.prev_tot = d_prev_;
     la.tr_S1 = cur_S1_;
     la.tr_S2 = cur_S2_;
+    la.gthr = gthr;
+    la.n_groups = groups;
     ZMC_HIP(launch_finalize(la, st));
     if (!stats_only) {
         if (any_thr) ZMC_HIP(launch_threshold(la, st));
+        if (groups) ZMC_HIP(launch_group_threshold(la, st));
         ZMC_HIP(launch_select(la, st));
         ZMC_HIP(hipMemcpyAsync(h_stats_, d_stats_, ns * sizeof(SegStats), hipMemcpyDeviceToHost, st));
     }
@@ -426,7 +455,7 @@ int Engine::next_list(hipStream_t st, std::vector<LiveSeg>& live, const std::vec
         h_segs2_[i].child_base = 0;
         if (split[i]) {
             HostSlot& hs = slots_[live[i].slot];
-            const int64_t nc = h_stats_[i].n_sel << hs.req.dim;
+            const int64_t nc = h_stats_[i].n_sel * kids_of(hs.req);
             h_segs2_[i].do_split = 1;
             h_segs2_[i].child_base = total;
             total += nc;

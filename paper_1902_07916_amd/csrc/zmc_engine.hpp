@@ -66,14 +66,19 @@ private:
 };
 
 // Tile shape of the sampling kernel per (integrand, dim, eval): the cap on
-// 4-point groups per thread per chunk (default 16).  Fixed per build or
+// 4-point groups per lane per chunk (default 32; a chunk is one wave's unit).  Fixed per build or
 // tuning file, never by the batch composition, so a request's result does
 // not depend on its company.
 struct TileTable {
     int groups[8][ZMC_MAX_DIM + 1][2];
     TileTable();
     int load(const char* path); // 0 on success
-    int get(int integrand, int dim, int eval) const { return groups[integrand][dim][eval]; }
+    int get(int integrand, int dim, int eval) const
+    {
+        // run-time compiled user integrands use the default cap
+        return (integrand >= 0 && integrand < 8) ? groups[integrand][dim][eval] : kDefaultGroups;
+    }
+    static constexpr int kDefaultGroups = 32;
 };
 
 // Host view of one resident integral.

@@ -20,19 +20,6 @@
 
 namespace zmc {
 
-constexpr int kSampleThreads = 256;
-
-struct SampleArgs {
-    const SlotDesc* slots;
-    const Segment* segs;
-    const BSeg* bsegs;
-    int32_t n_bsegs;
-    int32_t pad;
-    int64_t total_units;
-    const uint64_t* uid;
-    double2* partial;
-};
-
 struct LevelArgs {
     const SlotDesc* slots;
     const Segment* segs;
@@ -50,6 +37,8 @@ struct LevelArgs {
     double* tr_S1;           // optional per (cube, trial) sums (trace)
     double* tr_S2;
     uint64_t* next_uid;      // spawn output
+    double* gthr;            // per-parent thresholds, one per sibling group
+    int64_t n_groups;
 };
 
 struct RootArgs {
@@ -64,6 +53,7 @@ hipError_t launch_sample(int integrand, int dim, int eval, int grid, hipStream_t
 const void* sample_kernel_ptr(int integrand, int dim, int eval);
 hipError_t launch_finalize(const LevelArgs& a, hipStream_t st);
 hipError_t launch_threshold(const LevelArgs& a, hipStream_t st);
+hipError_t launch_group_threshold(const LevelArgs& a, hipStream_t st);
 hipError_t launch_select(const LevelArgs& a, hipStream_t st);
 hipError_t launch_spawn(const LevelArgs& a, hipStream_t st);
 hipError_t launch_roots(const RootArgs& a, hipStream_t st);

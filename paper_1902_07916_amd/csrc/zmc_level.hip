@@ -12,6 +12,8 @@
 // reproducible and independent of what else is resident.
 #include <float.h>
 
+#include <algorithm>
+
 #include "zmc_kernels.hpp"
 
 namespace zmc {
@@ -172,7 +174,7 @@ __global__ __launch_bounds__(kLevelThreads) void seg_mean_kernel(const LevelArgs
 {
     __shared__ double sh[kWaves];
     const Segment& sg = a.segs[blockIdx.x];
-    if (!sg.need_thr) return;
+    if (!sg.need_thr || sg.group_size) return;
     double v = 0.0;
     for (int64_t t = threadIdx.x; t < sg.n_tiles; t += kLevelThreads) v += a.tiles[sg.tile_base + t].sum_s;
     const double tot = block_sum(v, sh);
@@ -185,7 +187,7 @@ __global__ __launch_bounds__(kLevelThreads) void tile_sqdev_kernel(const LevelAr
     const int64_t tile = blockIdx.x;
     const int si = seg_of_tile(a.segs, a.n_segs, tile);
     const Segment& sg = a.segs[si];
-    if (!sg.need_thr) return;
+    if (!sg.need_thr || sg.group_size) return;
     const double mu = a.stats[si].mu;
     const int64_t first = (tile - sg.tile_base) * kTileCubes;
     double acc = 0.0;
@@ -203,7 +205,7 @@ __global__ __launch_bounds__(kLevelThreads) void seg_thr_kernel(const LevelArgs 
 {
     __shared__ double sh[kWaves];
     const Segment& sg = a.segs[blockIdx.x];
-    if (!sg.need_thr) return;
+    if (!sg.need_thr || sg.group_size) return;
     double v = 0.0;
     for (int64_t t = threadIdx.x; t < sg.n_tiles; t += kLevelThreads) v += a.tiles[sg.tile_base + t].sum_sq;
     const double tot = block_sum(v, sh);
@@ -211,6 +213,43 @@ __global__ __launch_bounds__(kLevelThreads) void seg_thr_kernel(const LevelArgs 
         const double sd = sqrt(tot / (double)sg.n_cubes);
         a.stats[blockIdx.x].sd = sd;
         a.stats[blockIdx.x].thr = a.stats[blockIdx.x].mu + a.slots[sg.slot].sigma_mult * sd;
+    }
+}
+
+// ---- per-parent thresholds: one per group of siblings -----------------------
+// One wave per group (groups of the segments with group_size > 0, in list
+// order): mean of the group's s, then the population std, in a fixed order.
+__device__ __forceinline__ int seg_of_group(const Segment* segs, int n, int64_t g)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].group_base <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kLevelThreads) void group_thr_kernel(const LevelArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t n_waves = (int64_t)gridDim.x * kWaves;
+    for (int64_t g = (int64_t)blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+         g < a.n_groups; g += n_waves) {
+        const int si = seg_of_group(a.segs, a.n_segs, g);
+        const Segment& sg = a.segs[si];
+        const int64_t gs = sg.group_size;
+        const double* s = a.s + sg.cube_base + (g - sg.group_base) * gs;
+        double v = 0.0;
+        for (int64_t j = lane; j < gs; j += 64) v += s[j];
+        const double mu = wave_sum(v) / (double)gs;
+        double q = 0.0;
+        for (int64_t j = lane; j < gs; j += 64) {
+            const double d = s[j] - mu;
+            q += d * d;
+        }
+        const double sd = sqrt(wave_sum(q) / (double)gs);
+        if (lane == 0) a.gthr[g] = mu + a.slots[sg.slot].sigma_mult * sd;
     }
 }
 
@@ -223,7 +262,7 @@ __global__ __launch_bounds__(kLevelThreads) void tile_select_kernel(const LevelA
     const int si = seg_of_tile(a.segs, a.n_segs, tile);
     const Segment& sg = a.segs[si];
     const bool thr_on = sg.need_thr != 0;
-    const double thr = thr_on ? a.stats[si].thr : 0.0;
+    const double level_thr = (thr_on && !sg.group_size) ? a.stats[si].thr : 0.0;
     const int64_t first = (tile - sg.tile_base) * kTileCubes;
     double accM = 0.0, accS2 = 0.0, selM = 0.0, selS2 = 0.0, margin = DBL_MAX;
     int64_t nsel = 0;
@@ -232,6 +271,7 @@ __global__ __launch_bounds__(kLevelThreads) void tile_select_kernel(const LevelA
         if (cl >= sg.n_cubes) break;
         const int64_t c = sg.cube_base + cl;
         const double m = a.m[c], s = a.s[c];
+        const double thr = (thr_on && sg.group_size) ? a.gthr[sg.group_base + cl / sg.group_size] : level_thr;
         const bool sel = thr_on && (s > thr);
         a.sel[c] = sel ? 1 : 0;
         if (sel) {
@@ -321,7 +361,7 @@ __global__ __launch_bounds__(kLevelThreads) void seg_decide_kernel(const LevelAr
     if (threadIdx.x == 0) {
         SegStats& S = a.stats[si];
         const double2 prev = a.prev_tot[si];
-        if (!sg.need_thr) {
+        if (!sg.need_thr || sg.group_size) {
             S.mu = S.sd = S.thr = __builtin_nan("");
         }
         S.min_margin = margin;
@@ -339,7 +379,7 @@ __global__ __launch_bounds__(kLevelThreads) void seg_decide_kernel(const LevelAr
             const double runM = totM + selM, runS2 = totS2 + selS2;
             if (sd.rtol > 0.0 && sqrt(runS2 / (double)(sd.trials - 1)) <= sd.rtol * fabs(runM)) {
                 dec = kRtolMet;
-            } else if (((uint64_t)nsel << sd.dim) > (uint64_t)sd.max_cubes) {
+            } else if ((uint64_t)nsel * (uint64_t)sd.kids > (uint64_t)sd.max_cubes) {
                 dec = kTruncated;
             } else {
                 dec = kSplit;
@@ -364,7 +404,9 @@ __global__ __launch_bounds__(kLevelThreads) void spawn_kernel(const LevelArgs a)
     const int si = seg_of_tile(a.segs, a.n_segs, tile);
     const Segment& sg = a.segs[si];
     if (!sg.do_split) return;
-    const int D = a.slots[sg.slot].dim;
+    const SlotDesc& sd = a.slots[sg.slot];
+    const int D = sd.dim;
+    const int64_t kids = sd.kids;
     const int64_t first = (tile - sg.tile_base) * kTileCubes;
     int base = 0;
     for (int j = 0; j < kPerThread; ++j) {
@@ -376,12 +418,19 @@ __global__ __launch_bounds__(kLevelThreads) void spawn_kernel(const LevelArgs a)
         base += total;
     }
     __syncthreads();
-    const int64_t n_writes = (int64_t)base << D;
-    const uint64_t mask = (1ull << D) - 1ull;
-    uint64_t* out = a.next_uid + sg.child_base + (a.tiles[tile].sel_prefix << D);
-    for (int64_t w = threadIdx.x; w < n_writes; w += kLevelThreads) {
-        const uint64_t parent = list[w >> D];
-        out[w] = (parent << D) | ((uint64_t)w & mask);
+    const int64_t n_writes = (int64_t)base * kids;
+    uint64_t* out = a.next_uid + sg.child_base + a.tiles[tile].sel_prefix * kids;
+    if (sd.split == 2) {
+        const uint64_t mask = (1ull << D) - 1ull;
+        for (int64_t w = threadIdx.x; w < n_writes; w += kLevelThreads) {
+            const uint64_t parent = list[w >> D];
+            out[w] = (parent << D) | ((uint64_t)w & mask);
+        }
+    } else {
+        for (int64_t w = threadIdx.x; w < n_writes; w += kLevelThreads) {
+            const int64_t i = w / kids;
+            out[w] = list[i] * (uint64_t)kids + (uint64_t)(w - i * kids);
+        }
     }
 }
 
@@ -443,6 +492,14 @@ hipError_t launch_threshold(const LevelArgs& a, hipStream_t st)
     hipLaunchKernelGGL(seg_mean_kernel, dim3(a.n_segs), dim3(kLevelThreads), 0, st, a);
     hipLaunchKernelGGL(tile_sqdev_kernel, dim3((unsigned)a.n_tiles), dim3(kLevelThreads), 0, st, a);
     hipLaunchKernelGGL(seg_thr_kernel, dim3(a.n_segs), dim3(kLevelThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_group_threshold(const LevelArgs& a, hipStream_t st)
+{
+    if (a.n_groups <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((a.n_groups + kWaves - 1) / kWaves, 65536);
+    hipLaunchKernelGGL(group_thr_kernel, dim3((unsigned)blocks), dim3(kLevelThreads), 0, st, a);
     return hipGetLastError();
 }
 

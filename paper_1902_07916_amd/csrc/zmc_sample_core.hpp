@@ -1,0 +1,212 @@
+// zmc_sample_core.hpp -- the body of the sampling kernel, shared by the
+// precompiled integrand registry (zmc_sample.hip) and the run-time compiled
+// user integrands (zmc_rtc.cpp): direct Monte Carlo over (cube, trial,
+// chunk) units with random numbers produced at the time of use (ZMCintegral,
+// Sec. 2.1 and Sec. 2.2).
+//
+// Work decomposition (gfx950, wave64): every wave takes one (cube, trial,
+// chunk) unit at a time, independently of the other waves of its block (no
+// LDS, no barrier).  A chunk is 4 * 64 * G points and lane l evaluates the
+// 4-point groups g = chunk*G*64 + l + 64*j, j < G.  One group of 4 points uses
+// D Philox blocks (4*D words, point q dimension i = word q*D + i), so counter
+// word 0 of block k is g*D + k; the other three counter words and the key are
+// wave-uniform (SGPRs).  Each lane sums f and f^2 in FP64 and the wave
+// reduces with a fixed butterfly, so a unit's partial sums depend only on the
+// unit and G.  The grid is persistent: wave w takes a contiguous range of
+// units, and only the first unit's segment is found by binary search.
+//
+// An integrand class I provides P64 / P32 parameter blocks, prep64 / prep32
+// (per cube, from the slot descriptor and the cube corner) and f64 / f32.
+#pragma once
+
+#include "zmc_device.hpp"
+
+namespace zmc {
+
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int D>
+__device__ __forceinline__ void corner(const SlotDesc& sd, int level, uint64_t uid, double* lo, double* h)
+{
+    uint64_t K[D];
+    const uint32_t d = (uint32_t)sd.divisions;
+    if (sd.split == 2) {
+        uint64_t root = (D * level >= 64) ? 0 : (uid >> (uint64_t)(D * level));
+        if (root < (1ull << 32)) {
+            uint32_t r32 = (uint32_t)root;
+#pragma unroll
+            for (int i = D - 1; i >= 0; --i) {
+                K[i] = r32 % d;
+                r32 /= d;
+            }
+        } else {
+#pragma unroll
+            for (int i = D - 1; i >= 0; --i) {
+                K[i] = root % d;
+                root /= d;
+            }
+        }
+        for (int j = 1; j <= level; ++j) {
+            const uint64_t c = uid >> (uint64_t)(D * (level - j));
+#pragma unroll
+            for (int i = 0; i < D; ++i) K[i] = 2u * K[i] + ((c >> (uint64_t)(D - 1 - i)) & 1u);
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            h[i] = ldexp(sd.h0[i], -level);
+            lo[i] = fma((double)K[i], h[i], sd.lower[i]);
+        }
+    } else {
+        // b-way splits: base-b^D path digits (per unit, so plain divisions)
+        const uint64_t b = (uint64_t)sd.split, kids = (uint64_t)sd.kids;
+        uint64_t root = uid;
+        for (int j = 0; j < level; ++j) root /= kids;
+#pragma unroll
+        for (int i = D - 1; i >= 0; --i) {
+            K[i] = root % d;
+            root /= d;
+        }
+        uint64_t parts = 1;
+        for (int j = 1; j <= level; ++j) {
+            uint64_t c = uid;
+            for (int t = 0; t < level - j; ++t) c /= kids;
+            c %= kids;
+            uint64_t digit[D];
+#pragma unroll
+            for (int i = D - 1; i >= 0; --i) {
+                digit[i] = c % b;
+                c /= b;
+            }
+#pragma unroll
+            for (int i = 0; i < D; ++i) K[i] = b * K[i] + digit[i];
+            parts *= b;
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            h[i] = sd.h0[i] / (double)parts;
+            lo[i] = fma((double)K[i], h[i], sd.lower[i]);
+        }
+    }
+}
+
+template <class I, int D, bool FP32>
+__device__ __forceinline__ void sample_units(const SampleArgs& a)
+{
+    constexpr int kWaves = kSampleThreads / 64;
+    const int lane = threadIdx.x & 63;
+    // the wave index is uniform over the wave: keep it (and all unit
+    // bookkeeping derived from it) in scalar registers
+    const int64_t wave = (int64_t)blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t n_waves = (int64_t)gridDim.x * kWaves;
+    const int64_t U = a.total_units;
+    const int64_t per = (U + n_waves - 1) / n_waves;
+    int64_t u = wave * per;
+    const int64_t uend = min(U, u + per);
+    if (u >= uend) return;
+
+    int bs = 0;
+    {
+        int hi = a.n_bsegs - 1;
+        while (bs < hi) {
+            const int mid = (bs + hi + 1) >> 1;
+            if (a.bsegs[mid].unit_base <= u) bs = mid;
+            else hi = mid - 1;
+        }
+    }
+
+    for (; u < uend; ++u) {
+        while (bs + 1 < a.n_bsegs && a.bsegs[bs + 1].unit_base <= u) ++bs;
+        const Segment& sg = a.segs[a.bsegs[bs].seg];
+        const SlotDesc& sd = a.slots[sg.slot];
+        const int64_t local = u - a.bsegs[bs].unit_base;
+        const int nch = sd.nch;
+        const int64_t upc = (int64_t)sd.trials * nch;
+        const int64_t cl = local / upc;
+        const int rem = (int)(local - cl * upc);
+        const int trial = rem / nch;
+        const int chunk = rem - trial * nch;
+        const uint64_t uid = a.uid[sg.cube_base + cl];
+        const int level = sg.level;
+
+        double lo[D], h[D];
+        corner<D>(sd, level, uid, lo, h);
+
+        const uint32_t k0 = (uint32_t)sd.seed, k1 = (uint32_t)(sd.seed >> 32);
+        const uint32_t c1 = (uint32_t)trial | ((uint32_t)level << 8);
+        const uint32_t c2 = (uint32_t)uid, c3 = (uint32_t)(uid >> 32);
+        const int64_t N = sd.samples;
+        const int G = sd.groups;
+        const int64_t g0 = (int64_t)chunk * G * 64 + lane;
+
+        double S1 = 0.0, S2 = 0.0;
+        if constexpr (FP32) {
+            typename I::P32 p;
+            I::prep32(sd, lo, h, p);
+            for (int j = 0; j < G; ++j) {
+                const int64_t g = g0 + (int64_t)j * 64;
+                const int64_t s0 = 4 * g;
+                if (s0 >= N) break;
+                const int nvalid = (int)min((int64_t)4, N - s0); // < 4 only in a ragged last group
+                uint32_t w[4 * D];
+                uint32_t ctr[D];
+                const uint32_t cb = (uint32_t)g * (uint32_t)D;
+#pragma unroll
+                for (int k = 0; k < D; ++k) ctr[k] = cb + (uint32_t)k;
+                philox4x32_10_lockstep<D>(ctr, c1, c2, c3, k0, k1, w);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    float v[D];
+#pragma unroll
+                    for (int i = 0; i < D; ++i) v[i] = unit_interval_f32(w[q * D + i]);
+                    float f = I::f32(p, v);
+                    f = (q < nvalid) ? f : 0.0f;
+                    const double fd = (double)f;
+                    S1 += fd;
+                    S2 = fma(fd, fd, S2);
+                }
+            }
+        } else {
+            typename I::P64 p;
+            I::prep64(sd, p);
+            double h24[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) h24[i] = ldexp(h[i], -24);
+            for (int j = 0; j < G; ++j) {
+                const int64_t g = g0 + (int64_t)j * 64;
+                const int64_t s0 = 4 * g;
+                if (s0 >= N) break;
+                const int nvalid = (int)min((int64_t)4, N - s0);
+                uint32_t w[4 * D];
+                uint32_t ctr[D];
+                const uint32_t cb = (uint32_t)g * (uint32_t)D;
+#pragma unroll
+                for (int k = 0; k < D; ++k) ctr[k] = cb + (uint32_t)k;
+                philox4x32_10_lockstep<D>(ctr, c1, c2, c3, k0, k1, w);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    double x[D];
+                    // x = fma(h, (2*(w>>9)+1) 2^-24, lo) computed as
+                    // fma(h 2^-24, (w>>8)|1, lo): the same exact product
+#pragma unroll
+                    for (int i = 0; i < D; ++i) x[i] = fma(h24[i], (double)((w[q * D + i] >> 8) | 1u), lo[i]);
+                    double f = I::f64(p, x);
+                    f = (q < nvalid) ? f : 0.0;
+                    S1 += f;
+                    S2 = fma(f, f, S2);
+                }
+            }
+        }
+
+        S1 = wave_sum(S1);
+        S2 = wave_sum(S2);
+        if (lane == 0) a.partial[sg.part_base + local] = make_double2(S1, S2);
+    }
+}
+
+} // namespace zmc

@@ -112,9 +112,10 @@ def main(argv=None) -> int:
     ap.add_argument("--dims", default="2-12")
     ap.add_argument("--integrands", default="genz_osc,genz_ppeak,genz_cpeak,genz_gauss,gauss,sin_sum")
     ap.add_argument("--evals", default="fp32")
+    ap.add_argument("--samples", type=int, default=16384, help="points per cube for --table")
     a = ap.parse_args(argv)
     if a.table:
-        rate_table()
+        rate_table(evals=a.evals.split(","), N=a.samples)
         return 0
     if not a.out:
         ap.error("--out is required unless --table")

@@ -53,6 +53,38 @@ def paper_f2(sigma=0.01, dim=9, divisions=3, samples=3**9, trials=5, max_depth=3
                 sigma_mult=sigma_mult, seed=seed, eval=eval)
 
 
+# The paper's own runs (Sec. 3), with its "partition depth" p mapped to
+# max_depth = p - 1 and "larger than k sigma" to sigma_mult = k.  Points per
+# sub-domain are n2^D where the paper gives points per dimension.
+PAPER_RUNS = {
+    # f1 = sin(sum x), [0,10]^6
+    "f1_tf": dict(f="f1", divisions=3, samples=20 ** 6, max_depth=1, sigma_mult=5.0,
+                  ref="TensorFlow version, Table 1: 3 sub-domains/axis, 20 points/axis, 5 trials, depth 2, 5 sigma"),
+    "f1_numba": dict(f="f1", divisions=6, samples=10 ** 6, max_depth=1, sigma_mult=5.0,
+                     ref="Numba multiprocessing version, Table 1: 6/axis, 10 points/axis, 5 trials, depth 2, 5 sigma"),
+    "f1_ray": dict(f="f1", divisions=12, samples=10 ** 4, max_depth=0, sigma_mult=5.0,
+                   ref="Numba-Ray version, Table 3: 12/axis, 1e4 points, 5 trials, depth 1"),
+    # normalised f2, sigma = 0.01, [-1,1]^9
+    "f2_numba": dict(f="f2", divisions=3, samples=3 ** 9, max_depth=3, sigma_mult=5.0,
+                     ref="Numba multiprocessing version, Table 2: 3/axis, 3 points/axis, 5 trials, depth 4, 5 sigma"),
+    "f2_ray": dict(f="f2", divisions=3, samples=10 ** 4, max_depth=3, sigma_mult=4.0,
+                   ref="Numba-Ray version, Table 4: 3/axis, 1e4 points, 5 trials, depth 4, 4 sigma"),
+}
+
+
+def paper_run(name, eval="fp32", seed=1):
+    """One of the paper's parameter sets (see PAPER_RUNS)."""
+    r = PAPER_RUNS[name]
+    if r["f"] == "f1":
+        w = sin6d(eval=eval, samples=r["samples"], divisions=r["divisions"], max_depth=r["max_depth"])
+        w["sigma_mult"] = r["sigma_mult"]
+    else:
+        w = paper_f2(divisions=r["divisions"], samples=r["samples"], max_depth=r["max_depth"],
+                     sigma_mult=r["sigma_mult"], eval=eval)
+    w["seed"] = seed
+    return w
+
+
 def _genz_params(fam, rng, D):
     c = rng.uniform(0.5, 5.0, D)
     w = rng.uniform(0.0, 1.0, D)

@@ -59,7 +59,12 @@ def test_invalid_arguments_are_rejected_before_any_device_call(lib):
            dict(integrand="monomial", params=[1.5, 2.0]), dict(rtol=-1.0),
            dict(samples=(1 << 33) + 4), dict(divisions=2, max_depth=15, params=[0.2, 1.0] + [0.0] * 2,
                                              lower=[-1.0] * 2, upper=[1.0] * 2, samples=4, trials=2) | {"divisions": 3000000},
-           dict(max_cubes_per_level=8)]
+           dict(max_cubes_per_level=8),
+           # k-way split and threshold scope (Sec. 2.1 variants)
+           dict(split=1), dict(split=65), dict(threshold_scope=2), dict(threshold_scope=-1),
+           dict(split=64, params=[0.2, 1.0] + [0.0] * 5, lower=[0.0] * 5, upper=[1.0] * 5),
+           dict(split=3, max_depth=9, divisions=2, params=[0.2, 1.0] + [0.0] * 5, lower=[0.0] * 5,
+                upper=[1.0] * 5)]
     for b in bad:
         r = _req(**b)
         out = _abi.Result()
@@ -114,3 +119,22 @@ def test_workloads_are_deterministic():
     assert 300 < len(s) < 500 and all(3 <= len(r["lower"]) <= 12 for _, r in s)
     assert all(1e-5 <= r["rtol"] <= 1e-3 for _, r in s)
     assert all(r["divisions"] ** len(r["lower"]) <= 4096 for _, r in s)
+
+
+def test_split_limits_agree_with_oracle(lib, orc):
+    """The library accepts exactly the (D, split, divisions, depth) shapes the
+    oracle accepts: children per split <= 2^24 and every uid below 2^64."""
+    from paper_1902_07916_amd import _abi, make_request
+    for D in (1, 2, 3, 5, 8, 12):
+        for b in (0, 2, 3, 5, 16, 64):
+            for d in (1, 3, 7):
+                for dep in (0, 1, 4, 7, 9, 15):
+                    prm = [0.2, 1.0] + [0.0] * D
+                    r = make_request("gauss", prm, [0.0] * D, [1.0] * D, d, 4, 3, dep, 1.0, 1, split=b)
+                    out = _abi.Result()
+                    rc = lib.zmc_integrate_request(C.byref(r), None, C.byref(out), None)
+                    p = orc.problem(0, D, [0.0] * D, [1.0] * D, d, 4, 3, dep, 1.0, 1, params=prm, split=b or 2)
+                    # the oracle checks d^D against the level cap when a run starts
+                    ok = orc.validate(p) == 0 and d ** D <= (1 << 24)
+                    assert (rc == _abi.ENOINIT) == ok, (D, b, d, dep, rc)
+                    assert rc in (_abi.ENOINIT, _abi.EINVAL)
