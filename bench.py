@@ -85,8 +85,9 @@ WORKLOADS = {
 }
 
 
-KERNEL_SOURCES = ("paper_1902_07916_amd/csrc/zmc_sample.hip", "paper_1902_07916_amd/csrc/zmc_integrands.hpp",
-                  "paper_1902_07916_amd/csrc/zmc_device.hpp", "paper_1902_07916_amd/csrc/zmc_kernels.hpp")
+KERNEL_SOURCES = ("paper_1902_07916_amd/csrc/zmc_sample.hip", "paper_1902_07916_amd/csrc/zmc_sample_core.hpp",
+                  "paper_1902_07916_amd/csrc/zmc_integrands.hpp", "paper_1902_07916_amd/csrc/zmc_device.hpp",
+                  "paper_1902_07916_amd/csrc/zmc_kernels.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sample_kernel.json")
 
 
@@ -146,7 +147,7 @@ def run_batch(a) -> dict:
     """Batched workload: n independent Genz integrals (D in 2..12) per step,
     all levels of all of them in shared launches."""
     import torch
-    from paper_1902_07916_amd import Integrator, request_from_dict, workloads
+    from paper_1902_07916_amd import INTEGRANDS, Integrator, request_from_dict, workloads
     ws = workloads.genz_batch(n=a.batch_n, max_cubes_per_level=a.batch_cap)
     reqs = [request_from_dict(w) for w in ws]
     zi = Integrator(arena_bytes=int(a.arena_gib * (1 << 30)), max_slots=max(8192, len(reqs)))
@@ -160,11 +161,23 @@ def run_batch(a) -> dict:
     zi.close()
     last = outs[-1]
     samples = sum(r.n_samples for o in outs for r in o)
-    k_ms = sum(sum(r.sample_ms_per_level) for r in last)  # per-integral copies of the shared level time
+    # algorithmic VALU slots of the last step: every sample of every level
+    names = {v: k for k, v in INTEGRANDS.items()}
+    slots = 0.0
+    for w, r in zip(ws, last):
+        per = valu_slots_per_sample(names[w["integrand"]], len(w["lower"]), w["eval"])["total"]
+        slots += per * sum(int(c) for c in r.cubes_per_level[:r.levels_run]) * w["trials"] * w["samples"]
+    # sampling-kernel time of the last step: integrals stepped together
+    # share one launch set per level, whose HIP-event time every one of them
+    # records; count each (level, time) once
+    k_ms = sum(ms for _, ms in {(l, float(r.sample_ms_per_level[l])) for r in last for l in range(r.levels_run)})
     return {"integrals_per_s": len(reqs) * a.steps / dt, "samples_per_s": samples / dt,
             "ms_per_step": dt * 1e3 / a.steps, "n_integrals": len(reqs),
             "status_ok": sum(r.status == 0 for r in last), "truncated": sum(bool(r.flags & 1) for r in last),
-            "cubes_total": sum(r.n_cubes for r in last), "samples_per_step": samples // a.steps}
+            "cubes_total": sum(r.n_cubes for r in last), "samples_per_step": samples // a.steps,
+            "sample_kernel_ms_per_step": k_ms,
+            "alu_frac_sampling": slots / (k_ms * 1e-3) / VALU_PEAK if k_ms > 0 else None,
+            "alu_frac_wall": slots / (dt / a.steps) / VALU_PEAK}
 
 
 def run_serve(a) -> dict:
