@@ -214,6 +214,9 @@ def run_serve(a) -> dict:
 # The paper's own timings on its hardware (Tables 1-4), seconds per run.
 PAPER_TIMES = {"f1_tf": (355.8, "1 x K40m"), "f1_numba": (313.5, "1 x K40m"), "f1_ray": (38.7, "1 x V100"),
                "f2_numba": (69.7, "1 x K40m"), "f2_ray": (4.8, "1 x V100")}
+# The paper's results for the same runs (Tables 1-4): value, standard deviation.
+PAPER_RESULTS = {"f1_tf": (-48.96, 0.76), "f1_numba": (-49.56, 1.40), "f1_ray": (-49.3971, 0.4845),
+                 "f2_numba": (1.00001, 0.00051), "f2_ray": (1.00035, 0.00064)}
 
 
 def run_paper(a) -> dict:
@@ -226,23 +229,27 @@ def run_paper(a) -> dict:
     zi = Integrator(arena_bytes=int(a.arena_gib * (1 << 30)))
     out = {}
     for name in workloads.PAPER_RUNS:
-        w = workloads.paper_run(name, eval="fp32", seed=1)
-        zi.integrate(**w)
-        torch.cuda.synchronize()
-        res, times = [], []
-        for seed in range(1, 11):
-            w = workloads.paper_run(name, eval="fp32", seed=seed)
-            t0 = time.perf_counter()
-            r = zi.integrate(**w)
-            times.append(time.perf_counter() - t0)
-            res.append(r)
-        vals = [r.integral for r in res]
-        out[name] = {"setting": workloads.PAPER_RUNS[name]["ref"], "mean": statistics.mean(vals),
-                     "spread": statistics.pstdev(vals), "mean_stderr": statistics.mean(r.stderr for r in res),
-                     "s_per_run": statistics.mean(times), "samples_per_run": res[0].n_samples,
-                     "samples_per_s": statistics.mean(r.n_samples for r in res) / statistics.mean(times),
-                     "levels": res[0].cubes_per_level,
-                     "paper_s_per_run": PAPER_TIMES[name][0], "paper_hw": PAPER_TIMES[name][1]}
+        row = {"setting": workloads.PAPER_RUNS[name]["ref"], "paper_result": PAPER_RESULTS[name],
+               "paper_s_per_run": PAPER_TIMES[name][0], "paper_hw": PAPER_TIMES[name][1]}
+        for ev in ("fp32", "fp64"):
+            zi.integrate(**workloads.paper_run(name, eval=ev, seed=1))
+            torch.cuda.synchronize()
+            res, times = [], []
+            for seed in range(1, 11):
+                w = workloads.paper_run(name, eval=ev, seed=seed)
+                t0 = time.perf_counter()
+                r = zi.integrate(**w)
+                times.append(time.perf_counter() - t0)
+                res.append(r)
+            vals = [r.integral for r in res]
+            row[ev] = {"mean": statistics.mean(vals), "spread": statistics.pstdev(vals),
+                       "mean_stderr": statistics.mean(r.stderr for r in res), "s_per_run": statistics.mean(times),
+                       "samples_per_run": statistics.mean(r.n_samples for r in res),
+                       "samples_per_s": statistics.mean(r.n_samples for r in res) / statistics.mean(times),
+                       "levels_seed1": res[0].cubes_per_level, "truncated": sum(bool(r.flags & 1) for r in res)}
+            print("%s %s: mean %.6g spread %.3g, %.4f s/run" % (name, ev, row[ev]["mean"], row[ev]["spread"],
+                                                             row[ev]["s_per_run"]), file=sys.stderr, flush=True)
+        out[name] = row
     zi.close()
     return out
 

@@ -3,8 +3,8 @@
     python -m paper_1902_07916_amd.tune --out tune.json [--dims 2-12] [--integrands genz_osc,...]
 
 For every (integrand, D, eval) bucket it times the sampling + per-cube
-reduction of a fixed list of root cubes (zmc_cube_estimates, N = 16384 points,
-3 trials) for each candidate cap on the 4-point groups a thread takes per
+reduction of a fixed list of root cubes (zmc_cube_estimates, N points per
+cube, 16384 unless --samples, 3 trials) for each candidate cap on the 4-point groups a thread takes per
 chunk (the chunk is 4 * 256 * groups points), and writes the fastest as a
 JSON object {"integrand:dim:eval": groups, ...} that zmc_init() reads from
 `tune_path`.  The table depends only on the bucket, never on what else is
@@ -43,7 +43,8 @@ def _params(name: str, D: int):
     raise ValueError(name)
 
 
-def time_bucket(name: str, D: int, eval_: str, groups: int, n_cubes: int = 4096, reps: int = 3) -> float:
+def time_bucket(name: str, D: int, eval_: str, groups: int, n_cubes: int = 4096, reps: int = 3,
+                N: int = 16384) -> float:
     """Seconds per sample of the sampling + reduction kernels with the given cap."""
     import numpy as np
     import torch
@@ -57,7 +58,7 @@ def time_bucket(name: str, D: int, eval_: str, groups: int, n_cubes: int = 4096,
         d = 2
         while d ** D < n_cubes and d < 64:
             d += 1
-        req = make_request(name, _params(name, D), [0.0] * D, [1.0] * D, d, 16384, 3, 0, 1.0, 1, eval=eval_)
+        req = make_request(name, _params(name, D), [0.0] * D, [1.0] * D, d, N, 3, 0, 1.0, 1, eval=eval_)
         n = min(n_cubes, d ** D)
         uids = np.arange(n, dtype=np.uint64)
         zi.cube_estimates(req, 0, uids, sums=False)
@@ -68,7 +69,7 @@ def time_bucket(name: str, D: int, eval_: str, groups: int, n_cubes: int = 4096,
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
         zi.close()
-        return dt / (n * 3 * 16384)
+        return dt / (n * 3 * N)
     finally:
         os.unlink(path)
 
@@ -112,7 +113,7 @@ def main(argv=None) -> int:
     ap.add_argument("--dims", default="2-12")
     ap.add_argument("--integrands", default="genz_osc,genz_ppeak,genz_cpeak,genz_gauss,gauss,sin_sum")
     ap.add_argument("--evals", default="fp32")
-    ap.add_argument("--samples", type=int, default=16384, help="points per cube for --table")
+    ap.add_argument("--samples", type=int, default=16384, help="points per cube")
     a = ap.parse_args(argv)
     if a.table:
         rate_table(evals=a.evals.split(","), N=a.samples)
@@ -126,7 +127,7 @@ def main(argv=None) -> int:
     for name in a.integrands.split(","):
         for D in _parse_dims(a.dims):
             for ev in a.evals.split(","):
-                times = {g: time_bucket(name, D, ev, g) for g in CANDIDATES}
+                times = {g: time_bucket(name, D, ev, g, N=a.samples) for g in CANDIDATES}
                 best = min(times, key=times.get)
                 key = "%d:%d:%d" % (INTEGRANDS[name], D, 1 if ev == "fp32" else 0)
                 table[key] = best

@@ -16,7 +16,7 @@ import numpy as np
 import pytest
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-from common import margin_band_ok, oracle_problem, rel, request  # noqa: E402
+from common import compare_tree, oracle_problem, rel, request  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -36,31 +36,7 @@ def zi():
 
 
 def _compare_tree(orc, w, r, eps, tol):
-    """Full-tree comparison of a traced GPU run with the oracle (replaying
-    the GPU's in-band decisions)."""
-    p = oracle_problem(orc, w)
-    replay = [(L["uid"], L["sel"]) for L in r.trace]
-    o = orc.integrate(p, replay=replay, band_eps=eps)
-    assert o.status == 0 and r.status == 0
-    assert len(o.levels) == r.levels_run
-    for l, (Lo, Lg) in enumerate(zip(o.levels, r.trace)):
-        assert Lg["n"] == Lo.n
-        assert len(Lg["uid"]) == Lg["n"], "trace capacity too small"
-        assert np.array_equal(Lg["uid"], Lo.uid), "level %d list differs" % l
-        # per-cube estimates
-        np.testing.assert_allclose(Lg["m"], Lo.m, rtol=tol, atol=tol * np.abs(Lo.m).max())
-        s_scale = max(np.abs(Lo.s).max(), 1e-12 * np.abs(Lo.m).max())
-        np.testing.assert_allclose(Lg["s"], Lo.s, rtol=max(tol, 1e-9) * 100, atol=tol * s_scale)
-        if l < w["max_depth"]:
-            assert rel(r.thr_per_level[l], Lo.thr) < max(tol, 1e-12) * 100
-            band = margin_band_ok(Lg["s"], Lg["sel"], Lo.thr, eps)
-            # outside the band the oracle decided the same (replay only inside)
-            keep = np.ones(Lo.n, bool)
-            keep[band] = False
-            assert np.array_equal(Lg["sel"][keep].astype(bool), Lo.sel[keep].astype(bool))
-    assert rel(r.integral, o.integral) < tol or abs(r.integral - o.integral) < tol * o.sum_abs
-    assert rel(r.std, o.std) < tol * 10
-    return o
+    return compare_tree(orc, w, r, eps, tol)
 
 
 def test_philox_words_bitwise(zi, orc):

@@ -10,11 +10,10 @@ by the oracle."""
 import os
 import sys
 
-import numpy as np
 import pytest
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-from common import oracle_problem, rel  # noqa: E402
+from common import compare_tree  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -33,46 +32,8 @@ def zi():
     z.close()
 
 
-def _cube_thresholds(orc, w, level, s):
-    """Each cube's threshold from the oracle's s: one per level (scope 0, or
-    the roots), else one per group of split^D siblings."""
-    D = len(w["lower"])
-    kids = (w.get("split", 0) or 2) ** D
-    if w.get("scope", 0) == 1 and level > 0:
-        assert len(s) % kids == 0
-        out = np.empty(len(s))
-        for g in range(0, len(s), kids):
-            out[g:g + kids] = orc.threshold(s[g:g + kids], w["sigma_mult"])[0]
-        return out
-    return np.full(len(s), orc.threshold(s, w["sigma_mult"])[0])
-
-
 def _compare(orc, w, r, eps, tol):
-    p = oracle_problem(orc, w)
-    replay = [(L["uid"], L["sel"]) for L in r.trace]
-    o = orc.integrate(p, replay=replay, band_eps=eps)
-    assert o.status == 0 and r.status == 0
-    assert len(o.levels) == r.levels_run
-    for l, (Lo, Lg) in enumerate(zip(o.levels, r.trace)):
-        assert Lg["n"] == Lo.n
-        assert np.array_equal(Lg["uid"], Lo.uid), "level %d list differs" % l
-        np.testing.assert_allclose(Lg["m"], Lo.m, rtol=tol, atol=tol * np.abs(Lo.m).max())
-        s_scale = max(np.abs(Lo.s).max(), 1e-12 * np.abs(Lo.m).max())
-        np.testing.assert_allclose(Lg["s"], Lo.s, rtol=max(tol, 1e-9) * 100, atol=tol * s_scale)
-        if l < w["max_depth"]:
-            thr = _cube_thresholds(orc, w, l, Lo.s)
-            sel = np.asarray(Lg["sel"]).astype(bool)
-            margin = np.abs(Lg["s"] - thr) / thr
-            out = margin > eps
-            assert np.array_equal(sel[out], (Lg["s"] > thr)[out]), "level %d selection" % l
-            assert np.array_equal(sel[out], Lo.sel[out].astype(bool))
-            if not np.isnan(Lo.thr):
-                assert rel(r.thr_per_level[l], Lo.thr) < max(tol, 1e-12) * 100
-            else:
-                assert np.isnan(r.thr_per_level[l])
-    assert rel(r.integral, o.integral) < tol or abs(r.integral - o.integral) < tol * o.sum_abs
-    assert rel(r.std, o.std) < tol * 10
-    return o
+    return compare_tree(orc, w, r, eps, tol)
 
 
 def _w(integrand, params, D, lo, hi, d, N, depth, sm, split, scope, eval_, seed=3):
