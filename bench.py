@@ -231,24 +231,31 @@ def run_paper(a) -> dict:
     for name in workloads.PAPER_RUNS:
         row = {"setting": workloads.PAPER_RUNS[name]["ref"], "paper_result": PAPER_RESULTS[name],
                "paper_s_per_run": PAPER_TIMES[name][0], "paper_hw": PAPER_TIMES[name][1]}
-        for ev in ("fp32", "fp64"):
-            zi.integrate(**workloads.paper_run(name, eval=ev, seed=1))
-            torch.cuda.synchronize()
-            res, times = [], []
-            for seed in range(1, 11):
-                w = workloads.paper_run(name, eval=ev, seed=seed)
-                t0 = time.perf_counter()
-                r = zi.integrate(**w)
-                times.append(time.perf_counter() - t0)
-                res.append(r)
-            vals = [r.integral for r in res]
-            row[ev] = {"mean": statistics.mean(vals), "spread": statistics.pstdev(vals),
-                       "mean_stderr": statistics.mean(r.stderr for r in res), "s_per_run": statistics.mean(times),
-                       "samples_per_run": statistics.mean(r.n_samples for r in res),
-                       "samples_per_s": statistics.mean(r.n_samples for r in res) / statistics.mean(times),
-                       "levels_seed1": res[0].cubes_per_level, "truncated": sum(bool(r.flags & 1) for r in res)}
-            print("%s %s: mean %.6g spread %.3g, %.4f s/run" % (name, ev, row[ev]["mean"], row[ev]["spread"],
-                                                             row[ev]["s_per_run"]), file=sys.stderr, flush=True)
+        # two readings of the split (bisection of every axis; d parts per
+        # axis as at the root) in both evaluation precisions
+        for reading, split in (("bisect", 0), ("kway", workloads.PAPER_RUNS[name]["divisions"])):
+            for ev in ("fp32", "fp64"):
+                zi.integrate(**workloads.paper_run(name, eval=ev, seed=1, split=split))
+                torch.cuda.synchronize()
+                res, times = [], []
+                for seed in range(1, 11):
+                    w = workloads.paper_run(name, eval=ev, seed=seed, split=split)
+                    t0 = time.perf_counter()
+                    r = zi.integrate(**w)
+                    times.append(time.perf_counter() - t0)
+                    res.append(r)
+                vals = [r.integral for r in res]
+                key = "%s_%s" % (reading, ev)
+                row[key] = {"mean": statistics.mean(vals), "spread": statistics.pstdev(vals),
+                            "mean_stderr": statistics.mean(r.stderr for r in res),
+                            "s_per_run": statistics.mean(times),
+                            "samples_per_run": statistics.mean(r.n_samples for r in res),
+                            "samples_per_s": statistics.mean(r.n_samples for r in res) / statistics.mean(times),
+                            "levels_seed1": res[0].cubes_per_level[:res[0].levels_run],
+                            "truncated": sum(bool(r.flags & 1) for r in res)}
+                print("%s %s: mean %.6g spread %.3g, %.4f s/run, levels %s" % (
+                    name, key, row[key]["mean"], row[key]["spread"], row[key]["s_per_run"],
+                    row[key]["levels_seed1"]), file=sys.stderr, flush=True)
         out[name] = row
     zi.close()
     return out

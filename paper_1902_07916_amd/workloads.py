@@ -72,8 +72,11 @@ PAPER_RUNS = {
 }
 
 
-def paper_run(name, eval="fp32", seed=1):
-    """One of the paper's parameter sets (see PAPER_RUNS)."""
+def paper_run(name, eval="fp32", seed=1, split=0):
+    """One of the paper's parameter sets (see PAPER_RUNS).  split = 0
+    bisects every axis of a selected cube; split = r["divisions"] is the
+    literal reading of Sec. 2.1 (a selected cube is cut into as many equal
+    parts as the domain was, d per axis)."""
     r = PAPER_RUNS[name]
     if r["f"] == "f1":
         w = sin6d(eval=eval, samples=r["samples"], divisions=r["divisions"], max_depth=r["max_depth"])
@@ -82,6 +85,7 @@ def paper_run(name, eval="fp32", seed=1):
         w = paper_f2(divisions=r["divisions"], samples=r["samples"], max_depth=r["max_depth"],
                      sigma_mult=r["sigma_mult"], eval=eval)
     w["seed"] = seed
+    w["split"] = split
     return w
 
 
