@@ -20,10 +20,14 @@
  *  3. Per cube: m = mean of the I_t, s = population std of the I_t.
  *  4. Per level and per integral: thr = mean(s) + sigma_mult * std(s)
  *     (population std); a cube with s > thr is split (unless the level is
- *     max_depth), all other cubes are accepted with their m.
+ *     max_depth), all other cubes are accepted with their m.  With
+ *     threshold_scope = 1, below the roots each split parent's children get
+ *     their own threshold from their own s.
  *  5. A split cube is replaced by its 2^D children (every axis bisected);
  *     child c of uid has uid' = (uid << D) | c, bit (D-1-i) of c choosing the
- *     upper half of axis i.  The same estimate is run on the new list.
+ *     upper half of axis i.  With split = b every axis is cut into b parts:
+ *     uid' = uid * b^D + c, digit (D-1-i) of c in base b giving axis i.  The
+ *     same estimate is run on the new list.
  *  6. Result: integral = sum of accepted m; std = sqrt(sum of accepted s^2);
  *     stderr = sqrt(sum s^2 / (n1 - 1)).
  *
