@@ -239,7 +239,8 @@ int zmc_submit(const zmc_request* req, uint64_t* ticket);
 int zmc_poll(uint64_t ticket, zmc_result* out, int wait);
 
 /* Cancel a queued or running request; its poll then returns a result with
- * status ECANCELED.  ENOTFOUND for unknown tickets. */
+ * status ECANCELED.  A request that has already finished keeps its result
+ * (ZMC_OK, no effect).  ENOTFOUND for unknown or already-collected tickets. */
 int zmc_cancel(uint64_t ticket);
 
 /* Serving counters: queued, resident, completed, levels stepped. */

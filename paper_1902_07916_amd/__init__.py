@@ -132,7 +132,8 @@ class Integrator:
 
     arena_bytes: device memory for all levels of the trees; serve: start the
     serving thread on its own stream (the arena is split 1/4 synchronous,
-    3/4 serving)."""
+    3/4 serving).  The library holds one context per process: opening an
+    Integrator closes the one open before it, whose calls then raise."""
 
     _active = None
 
@@ -176,6 +177,12 @@ class Integrator:
     def __exit__(self, *exc):
         self.close()
 
+    def _live(self):
+        if not getattr(self, "_open", False):
+            raise RuntimeError("this Integrator is closed (the library holds one context per process, and opening "
+                               "another Integrator closes the previous one)")
+        return self._lib
+
     @staticmethod
     def _stream():
         import torch
@@ -192,6 +199,7 @@ class Integrator:
 
     def integrate_request(self, req: _abi.Request, trace: bool = False, trace_capacity: int = 1 << 20,
                           raise_on_error: bool = True) -> Result:
+        self._live()
         out = _abi.Result()
         tr = None
         bufs = None
@@ -207,6 +215,7 @@ class Integrator:
         return Result.from_c(out, tdict)
 
     def integrate_batch(self, reqs) -> list:
+        self._live()
         arr = (_abi.Request * len(reqs))(*reqs)
         outs = (_abi.Result * len(reqs))()
         rc = self._lib.zmc_integrate_batch(arr, len(reqs), self._stream(), outs)
@@ -216,11 +225,13 @@ class Integrator:
 
     # -- serving ---------------------------------------------------------------
     def submit(self, req: _abi.Request) -> int:
+        self._live()
         t = C.c_uint64()
         check(self._lib.zmc_submit(C.byref(req), C.byref(t)), "zmc_submit")
         return t.value
 
     def poll(self, ticket: int, wait: bool = False):
+        self._live()
         out = _abi.Result()
         rc = self._lib.zmc_poll(ticket, C.byref(out), 1 if wait else 0)
         if rc == _abi.EAGAIN:
@@ -229,15 +240,18 @@ class Integrator:
         return Result.from_c(out)
 
     def cancel(self, ticket: int):
+        self._live()
         check(self._lib.zmc_cancel(ticket), "zmc_cancel")
 
     def serve_stats(self):
+        self._live()
         out = (C.c_uint64 * 4)()
         check(self._lib.zmc_serve_stats(out), "zmc_serve_stats")
         return dict(queued=out[0], resident=out[1], completed=out[2], levels=out[3])
 
     # -- step-level access for parity checks -----------------------------------
     def debug_philox(self, key, ctr: np.ndarray) -> np.ndarray:
+        self._live()
         ctr = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(-1, 4)
         out = np.zeros_like(ctr)
         check(self._lib.zmc_debug_philox(int(key[0]), int(key[1]), ctr.ctypes.data_as(C.POINTER(C.c_uint32)),
@@ -246,6 +260,7 @@ class Integrator:
         return out
 
     def debug_points(self, req: _abi.Request, level: int, uid: int, trial: int, s0: int, n: int) -> np.ndarray:
+        self._live()
         x = np.zeros((n, req.dim), dtype=np.float64)
         check(self._lib.zmc_debug_points(C.byref(req), level, int(uid), trial, s0, n,
                                          x.ctypes.data_as(C.POINTER(C.c_double)), self._stream()),
@@ -253,6 +268,7 @@ class Integrator:
         return x
 
     def cube_estimates(self, req: _abi.Request, level: int, uids, sums: bool = True):
+        self._live()
         uids = np.ascontiguousarray(uids, dtype=np.uint64)
         n = len(uids)
         m = np.zeros(n)

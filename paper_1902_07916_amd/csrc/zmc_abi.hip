@@ -422,6 +422,7 @@ int zmc_cancel(uint64_t ticket)
     if (!g.inited || !g.server) return fail(ZMC_ENOINIT, "serving is not configured");
     Server* S = g.server;
     std::lock_guard<std::mutex> lk(S->mu);
+    if (S->done.count(ticket)) return ZMC_OK; // finished already: its result stands
     if (!S->pending.count(ticket)) return fail(ZMC_ENOTFOUND, "unknown ticket");
     for (auto it = S->queue.begin(); it != S->queue.end(); ++it) {
         if (it->ticket == ticket) {

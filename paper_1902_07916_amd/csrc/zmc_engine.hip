@@ -34,6 +34,13 @@ uint64_t ipow_u64(uint64_t b, int e)
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Packed per-level tables: segments at 0, running totals, bucket segments.
+size_t prev_offset(int ns) { return align256((size_t)ns * sizeof(Segment)); }
+size_t bseg_offset(int ns) { return prev_offset(ns) + align256((size_t)ns * sizeof(double2)); }
+size_t table_bytes(int max_segs) { return bseg_offset(max_segs) + (size_t)max_segs * sizeof(BSeg); }
+
 // parts per axis when a cube is split (0 in a request means bisection)
 int split_of(const zmc_request& r) { return r.split ? r.split : 2; }
 
@@ -103,24 +110,31 @@ int Engine::setup(char* base, size_t bytes, int max_slots, const TileTable* tile
         return p;
     };
     d_slots_ = (SlotDesc*)carve(sizeof(SlotDesc) * max_slots);
-    d_segs_ = (Segment*)carve(sizeof(Segment) * max_slots);
-    d_bsegs_ = (BSeg*)carve(sizeof(BSeg) * max_slots);
+    // per-level tables (segments, running totals, bucket segments), packed
+    // so that one copy uploads them; the offsets depend on the level's size
+    tab_bytes_ = table_bytes(max_slots);
+    d_tab_ = carve(tab_bytes_);
     d_stats_ = (SegStats*)carve(sizeof(SegStats) * max_slots);
-    d_prev_ = (double2*)carve(sizeof(double2) * max_slots);
     d_rootsegs_ = (Segment*)carve(sizeof(Segment) * max_slots);
+    d_seg_count_ = (int32_t*)carve(sizeof(int32_t) * max_slots);
     off = (off + 255) & ~(size_t)255;
     if (off + (16u << 20) > bytes) {
         set_error("arena too small for the slot tables");
         return ZMC_EINVAL;
     }
     arena_.init(base + off, bytes - off);
+    // the tile counters start at 0 and every launch leaves them at 0
+    ZMC_HIP(hipMemset(d_seg_count_, 0, sizeof(int32_t) * max_slots));
     ZMC_HIP(hipHostMalloc((void**)&h_slots_, sizeof(SlotDesc) * max_slots, hipHostMallocDefault));
-    ZMC_HIP(hipHostMalloc((void**)&h_segs_, sizeof(Segment) * max_slots, hipHostMallocDefault));
+    ZMC_HIP(hipHostMalloc((void**)&h_tab_, tab_bytes_, hipHostMallocDefault));
     ZMC_HIP(hipHostMalloc((void**)&h_segs2_, sizeof(Segment) * max_slots, hipHostMallocDefault));
     ZMC_HIP(hipHostMalloc((void**)&h_rootsegs_, sizeof(Segment) * max_slots, hipHostMallocDefault));
-    ZMC_HIP(hipHostMalloc((void**)&h_bsegs_, sizeof(BSeg) * max_slots, hipHostMallocDefault));
-    ZMC_HIP(hipHostMalloc((void**)&h_stats_, sizeof(SegStats) * max_slots, hipHostMallocDefault));
-    ZMC_HIP(hipHostMalloc((void**)&h_prev_, sizeof(double2) * max_slots, hipHostMallocDefault));
+    // the decision kernel writes each level's per-segment records straight
+    // into this mapped host buffer, read after the level's synchronisation
+    ZMC_HIP(hipHostMalloc((void**)&h_stats_, sizeof(SegStats) * max_slots, hipHostMallocMapped));
+    ZMC_HIP(hipHostGetDevicePointer((void**)&d_hstats_, h_stats_, 0));
+    h_segs_ = (Segment*)h_tab_;
+    d_segs_ = (Segment*)d_tab_;
     ZMC_HIP(hipDeviceGetAttribute(&n_cu_, hipDeviceAttributeMultiprocessorCount, device));
     ZMC_HIP(hipEventCreate(&ev_sample0_));
     ZMC_HIP(hipEventCreate(&ev_sample1_));
@@ -130,13 +144,14 @@ int Engine::setup(char* base, size_t bytes, int max_slots, const TileTable* tile
 
 void Engine::teardown()
 {
-    void* hs[] = {h_slots_, h_segs_, h_segs2_, h_rootsegs_, h_bsegs_, h_stats_, h_prev_};
+    void* hs[] = {h_slots_, h_tab_, h_segs2_, h_rootsegs_, h_stats_};
     for (void* p : hs)
         if (p) (void)hipHostFree(p);
     h_slots_ = nullptr;
+    h_tab_ = nullptr;
     h_segs_ = h_segs2_ = h_rootsegs_ = nullptr;
     h_bsegs_ = nullptr;
-    h_stats_ = nullptr;
+    h_stats_ = d_hstats_ = nullptr;
     h_prev_ = nullptr;
     if (ev_sample0_) (void)hipEventDestroy(ev_sample0_);
     if (ev_sample1_) (void)hipEventDestroy(ev_sample1_);
@@ -274,10 +289,18 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
     const int ns = (int)live.size();
     int64_t cube = 0, part = 0, tile = 0, groups = 0;
     bool any_thr = false;
+    h_prev_ = (double2*)(h_tab_ + prev_offset(ns));
+    h_bsegs_ = (BSeg*)(h_tab_ + bseg_offset(ns));
+    d_prev_ = (double2*)(d_tab_ + prev_offset(ns));
+    d_bsegs_ = (BSeg*)(d_tab_ + bseg_offset(ns));
     for (int i = 0; i < ns; ++i) {
         HostSlot& hs = slots_[live[i].slot];
         const zmc_request& r = hs.req;
         const int64_t n = live[i].n_cubes;
+        if (n < 1) {
+            set_error("internal: empty segment in a level list");
+            return ZMC_EINVAL;
+        }
         Segment& g = h_segs_[i];
         memset(&g, 0, sizeof(g));
         g.slot = live[i].slot;
@@ -328,8 +351,6 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
         return ZMC_ENOMEM;
     }
 
-    ZMC_HIP(hipMemcpyAsync(d_segs_, h_segs_, ns * sizeof(Segment), hipMemcpyHostToDevice, st));
-    ZMC_HIP(hipMemcpyAsync(d_prev_, h_prev_, ns * sizeof(double2), hipMemcpyHostToDevice, st));
 
     // sampling: one persistent launch per (integrand, dim, eval) bucket
     std::map<int, std::vector<int>> buckets;
@@ -363,7 +384,7 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
         L.units = u;
         launches.push_back(L);
     }
-    ZMC_HIP(hipMemcpyAsync(d_bsegs_, h_bsegs_, nb * sizeof(BSeg), hipMemcpyHostToDevice, st));
+    ZMC_HIP(hipMemcpyAsync(d_tab_, h_tab_, bseg_offset(ns) + (size_t)nb * sizeof(BSeg), hipMemcpyHostToDevice, st));
     ZMC_HIP(hipEventRecord(ev_sample0_, st));
     int n_launch = 0;
     for (const Launch& L : launches) {
@@ -406,12 +427,13 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
     la.tr_S2 = cur_S2_;
     la.gthr = gthr;
     la.n_groups = groups;
+    la.seg_count = d_seg_count_;
+    la.host_stats = stats_only ? nullptr : d_hstats_;
     ZMC_HIP(launch_finalize(la, st));
     if (!stats_only) {
         if (any_thr) ZMC_HIP(launch_threshold(la, st));
         if (groups) ZMC_HIP(launch_group_threshold(la, st));
         ZMC_HIP(launch_select(la, st));
-        ZMC_HIP(hipMemcpyAsync(h_stats_, d_stats_, ns * sizeof(SegStats), hipMemcpyDeviceToHost, st));
     }
     if (trace && ns == 1) {
         const HostSlot& hs = slots_[live[0].slot];

@@ -152,6 +152,11 @@ private:
     const TileTable* tiles_ = nullptr;
     // fixed device tables
     SlotDesc* d_slots_ = nullptr;
+    char* d_tab_ = nullptr;
+    char* h_tab_ = nullptr;
+    size_t tab_bytes_ = 0;
+    int32_t* d_seg_count_ = nullptr;
+    SegStats* d_hstats_ = nullptr;
     Segment* d_segs_ = nullptr;
     Segment* d_rootsegs_ = nullptr;
     BSeg* d_bsegs_ = nullptr;

@@ -39,6 +39,8 @@ struct LevelArgs {
     uint64_t* next_uid;      // spawn output
     double* gthr;            // per-parent thresholds, one per sibling group
     int64_t n_groups;
+    int32_t* seg_count;      // per segment: tile blocks done (0 between kernels)
+    SegStats* host_stats;    // optional mapped host copy of the decisions
 };
 
 struct RootArgs {

@@ -5,11 +5,15 @@
 //
 // All of these are HBM-bound and small next to the sampling kernel.  The
 // per-cube kernels work on tiles of 1024 consecutive cubes of one segment
-// (256 threads, 4 cubes each, strided so that loads coalesce); per-integral
-// kernels run one 256-thread block per segment over that segment's tiles.
-// Every reduction has a fixed shape (thread-serial over its elements, then
-// wave64 butterflies, then the 4 waves in order), so results are bitwise
-// reproducible and independent of what else is resident.
+// (256 threads, 4 cubes each, strided so that loads coalesce).  The
+// per-integral step that follows each of them (the mean of s, the threshold,
+// the decision) runs in the same launch: the last tile block of a segment to
+// finish, found with a per-segment counter, reduces that segment's tile
+// records in tile order.  A level therefore costs three short launches after
+// sampling.  Every reduction has a fixed shape (thread-serial over its
+// elements, then wave64 butterflies, then the 4 waves in order), so results
+// are bitwise reproducible and independent of which block finishes last or
+// of what else is resident.
 #include <float.h>
 
 #include <algorithm>
@@ -114,6 +118,51 @@ __device__ __forceinline__ int seg_of_tile(const Segment* segs, int n, int64_t t
     return lo;
 }
 
+// Called by every tile block of segment si once its tile record is written:
+// true in the block that completes the segment, which then sees every other
+// block's records.  The counter is back at 0 when the launch ends.
+__device__ bool last_tile_of_segment(int32_t* count, int si, int64_t n_tiles)
+{
+    __shared__ int last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence(); // release this block's tile record
+        const int old = atomicAdd(&count[si], 1);
+        last = (old == (int)n_tiles - 1);
+        if (last) atomicExch(&count[si], 0);
+    }
+    __syncthreads();
+    if (last) __threadfence(); // acquire the other blocks' records
+    return last != 0;
+}
+
+// ---- per-segment steps (one block) ------------------------------------------
+__device__ void seg_mean(const LevelArgs& a, int si)
+{
+    __shared__ double sh[kWaves];
+    const Segment& sg = a.segs[si];
+    double v = 0.0;
+    for (int64_t t = threadIdx.x; t < sg.n_tiles; t += kLevelThreads) v += a.tiles[sg.tile_base + t].sum_s;
+    const double tot = block_sum(v, sh);
+    if (threadIdx.x == 0) a.stats[si].mu = tot / (double)sg.n_cubes;
+}
+
+__device__ void seg_thr(const LevelArgs& a, int si)
+{
+    __shared__ double sh[kWaves];
+    const Segment& sg = a.segs[si];
+    double v = 0.0;
+    for (int64_t t = threadIdx.x; t < sg.n_tiles; t += kLevelThreads) v += a.tiles[sg.tile_base + t].sum_sq;
+    const double tot = block_sum(v, sh);
+    if (threadIdx.x == 0) {
+        const double sd = sqrt(tot / (double)sg.n_cubes);
+        a.stats[si].sd = sd;
+        a.stats[si].thr = a.stats[si].mu + a.slots[sg.slot].sigma_mult * sd;
+    }
+}
+
+__device__ void seg_decide(const LevelArgs& a, int si);
+
 // ---- finalize: per cube I_t = V * S1_t / N, m = mean I_t, s = std I_t ------
 __global__ __launch_bounds__(kLevelThreads) void finalize_kernel(const LevelArgs a)
 {
@@ -167,20 +216,10 @@ __global__ __launch_bounds__(kLevelThreads) void finalize_kernel(const LevelArgs
         a.tiles[tile].sum_s = tot;
         a.tiles[tile].nonfinite = any_bad;
     }
+    if (sg.need_thr && !sg.group_size && last_tile_of_segment(a.seg_count, si, sg.n_tiles)) seg_mean(a, si);
 }
 
-// ---- threshold: mean of s, then std of s, per segment ----------------------
-__global__ __launch_bounds__(kLevelThreads) void seg_mean_kernel(const LevelArgs a)
-{
-    __shared__ double sh[kWaves];
-    const Segment& sg = a.segs[blockIdx.x];
-    if (!sg.need_thr || sg.group_size) return;
-    double v = 0.0;
-    for (int64_t t = threadIdx.x; t < sg.n_tiles; t += kLevelThreads) v += a.tiles[sg.tile_base + t].sum_s;
-    const double tot = block_sum(v, sh);
-    if (threadIdx.x == 0) a.stats[blockIdx.x].mu = tot / (double)sg.n_cubes;
-}
-
+// ---- threshold: std of s around the mean, per segment ----------------------
 __global__ __launch_bounds__(kLevelThreads) void tile_sqdev_kernel(const LevelArgs a)
 {
     __shared__ double sh[kWaves];
@@ -199,21 +238,7 @@ __global__ __launch_bounds__(kLevelThreads) void tile_sqdev_kernel(const LevelAr
     }
     const double tot = block_sum(acc, sh);
     if (threadIdx.x == 0) a.tiles[tile].sum_sq = tot;
-}
-
-__global__ __launch_bounds__(kLevelThreads) void seg_thr_kernel(const LevelArgs a)
-{
-    __shared__ double sh[kWaves];
-    const Segment& sg = a.segs[blockIdx.x];
-    if (!sg.need_thr || sg.group_size) return;
-    double v = 0.0;
-    for (int64_t t = threadIdx.x; t < sg.n_tiles; t += kLevelThreads) v += a.tiles[sg.tile_base + t].sum_sq;
-    const double tot = block_sum(v, sh);
-    if (threadIdx.x == 0) {
-        const double sd = sqrt(tot / (double)sg.n_cubes);
-        a.stats[blockIdx.x].sd = sd;
-        a.stats[blockIdx.x].thr = a.stats[blockIdx.x].mu + a.slots[sg.slot].sigma_mult * sd;
-    }
+    if (last_tile_of_segment(a.seg_count, si, sg.n_tiles)) seg_thr(a, si);
 }
 
 // ---- per-parent thresholds: one per group of siblings -----------------------
@@ -299,15 +324,14 @@ __global__ __launch_bounds__(kLevelThreads) void tile_select_kernel(const LevelA
         T.min_margin = tMargin;
         T.n_sel = tSel;
     }
+    if (last_tile_of_segment(a.seg_count, si, sg.n_tiles)) seg_decide(a, si);
 }
 
 // ---- per segment: totals, stop rules, rank base of every tile --------------
-__global__ __launch_bounds__(kLevelThreads) void seg_decide_kernel(const LevelArgs a)
+__device__ void seg_decide(const LevelArgs& a, int si)
 {
     __shared__ double sh[kWaves];
     __shared__ int64_t shi[kWaves];
-    __shared__ int shf[kWaves];
-    const int si = blockIdx.x;
     const Segment& sg = a.segs[si];
     const SlotDesc& sd = a.slots[sg.slot];
     double accM = 0.0, accS2 = 0.0, selM = 0.0, selS2 = 0.0, margin = DBL_MAX;
@@ -356,7 +380,6 @@ __global__ __launch_bounds__(kLevelThreads) void seg_decide_kernel(const LevelAr
         if (t < sg.n_tiles) a.tiles[sg.tile_base + t].sel_prefix = base + x - v;
         carry += chunk;
     }
-    (void)shf;
 
     if (threadIdx.x == 0) {
         SegStats& S = a.stats[si];
@@ -392,6 +415,10 @@ __global__ __launch_bounds__(kLevelThreads) void seg_decide_kernel(const LevelAr
         S.decision = dec;
         S.totM = totM;
         S.totS2 = totS2;
+        if (a.host_stats) {
+            a.host_stats[si] = S;
+            __threadfence_system();
+        }
     }
 }
 
@@ -489,9 +516,7 @@ hipError_t launch_finalize(const LevelArgs& a, hipStream_t st)
 hipError_t launch_threshold(const LevelArgs& a, hipStream_t st)
 {
     if (a.n_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(seg_mean_kernel, dim3(a.n_segs), dim3(kLevelThreads), 0, st, a);
     hipLaunchKernelGGL(tile_sqdev_kernel, dim3((unsigned)a.n_tiles), dim3(kLevelThreads), 0, st, a);
-    hipLaunchKernelGGL(seg_thr_kernel, dim3(a.n_segs), dim3(kLevelThreads), 0, st, a);
     return hipGetLastError();
 }
 
@@ -507,7 +532,6 @@ hipError_t launch_select(const LevelArgs& a, hipStream_t st)
 {
     if (a.n_tiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(tile_select_kernel, dim3((unsigned)a.n_tiles), dim3(kLevelThreads), 0, st, a);
-    hipLaunchKernelGGL(seg_decide_kernel, dim3(a.n_segs), dim3(kLevelThreads), 0, st, a);
     return hipGetLastError();
 }
 

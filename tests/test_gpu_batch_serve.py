@@ -103,11 +103,27 @@ def test_serving_mix_matches_alone(zi, orc):
 
 def test_serving_cancel_and_errors(zi):
     from paper_1902_07916_amd import ZmcError, make_request
-    big = make_request("genz_osc", [0.1] + [2.0] * 8, [0.0] * 8, [1.0] * 8, 3, 1 << 16, 3, 4, 5.0, 1, eval="fp32")
+    # ~2e10 points per level: still running when the cancel arrives, unless
+    # the submitting thread is descheduled for that long
+    big = make_request("genz_osc", [0.1] + [2.0] * 8, [0.0] * 8, [1.0] * 8, 3, 1 << 20, 3, 4, 5.0, 1, eval="fp32")
     t = zi.submit(big)
     zi.cancel(t)
     r = zi.poll(t, wait=True)
     assert r.status in (0, -8)
+    with pytest.raises(ZmcError):
+        zi.cancel(t)      # collected: unknown now
+    # a finished, uncollected request keeps its result when cancelled
+    small = make_request("gauss", [0.2, 1.0, 0.0, 0.0], [-1.0] * 2, [1.0] * 2, 4, 256, 3, 1, 1.0, 1)
+    t2 = zi.submit(small)
+    deadline = time.time() + 30
+    while time.time() < deadline:
+        st = zi.serve_stats()
+        if st["queued"] == 0 and st["resident"] == 0:
+            break
+        time.sleep(0.001)
+    zi.cancel(t2)
+    r2 = zi.poll(t2, wait=True)
+    assert r2.status == 0 and r2.integral > 0
     with pytest.raises(ZmcError):
         zi.poll(t)        # collected already
     with pytest.raises(ZmcError):

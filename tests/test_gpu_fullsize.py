@@ -153,7 +153,7 @@ def test_gauss4d_full_vs_closed_form(zi):
     assert abs(r.integral - exact) <= 5 * r.stderr
 
 
-def test_genz_batch4096_full():
+def test_genz_batch4096_full(zi):
     """The 4096-integral Genz batch exactly as the benchmark runs it (D = 2..12,
     N = 4096, n1 = 3, max_depth 2, sigma 5, level cap 2^20, FP32 evaluation).
 
@@ -163,48 +163,42 @@ def test_genz_batch4096_full():
     integrals of each family small enough for the oracle: the batch result is
     bitwise the same as the request alone, and the alone run's whole tree
     matches the oracle (replaying in-band decisions) within 1e-4."""
-    import torch
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
     from common import compare_tree
-    from paper_1902_07916_amd import Integrator, request_from_dict
+    from paper_1902_07916_amd import request_from_dict
     from paper_1902_07916_amd import workloads as W
     import oracle as orc
     ws = W.genz_batch(n=4096, max_cubes_per_level=1 << 20)
-    z = Integrator(arena_bytes=48 << 30, max_slots=8192)
-    try:
-        print("batch 4096: integrating", flush=True)
-        outs = z.integrate_batch([request_from_dict(w) for w in ws])
-        for w, r in zip(ws, outs):
-            D = len(w["lower"])
-            assert r.status == 0
-            n = [int(c) for c in r.cubes_per_level[:r.levels_run]]
-            sel = [int(c) for c in r.selected_per_level[:r.levels_run]]
-            assert n[0] == w["divisions"] ** D
-            assert r.n_samples == sum(n) * w["trials"] * w["samples"]
-            for l in range(r.levels_run):
-                assert sel[l] <= math.floor(n[l] / (1 + w["sigma_mult"] ** 2))
-                if l + 1 < r.levels_run:
-                    assert n[l + 1] == sel[l] * 2 ** D <= w["max_cubes_per_level"]
-            if r.flags & 1:
-                assert sel[r.levels_run - 1] * 2 ** D > w["max_cubes_per_level"]
-        # per family, two integrals the oracle can run in about a second
-        # (300..3000 cubes in all), refined ones first
-        picks = []
-        for fam in W.GENZ_FAMILIES:
-            idx = [i for i, w in enumerate(ws) if w["integrand"] == fam and 300 <= outs[i].n_cubes <= 3000]
-            idx.sort(key=lambda i: (-outs[i].levels_run, outs[i].n_cubes))
-            picks += idx[:2]
-        assert len(picks) >= 6
-        for i in picks:
-            w = ws[i]
-            print("batch 4096: integral %d alone (family %d, D=%d, %d cubes)" % (
-                i, w["integrand"], len(w["lower"]), outs[i].n_cubes), flush=True)
-            ra = z.integrate(**w, trace=True)
-            assert ra.integral == outs[i].integral and ra.std == outs[i].std
-            compare_tree(orc, w, ra, 1e-4, 1e-4)
-    finally:
-        z.close()
+    z = zi  # 48 GiB arena, 8192 slots: the benchmark's configuration
+    print("batch 4096: integrating", flush=True)
+    outs = z.integrate_batch([request_from_dict(w) for w in ws])
+    for w, r in zip(ws, outs):
+        D = len(w["lower"])
+        assert r.status == 0
+        n = [int(c) for c in r.cubes_per_level[:r.levels_run]]
+        sel = [int(c) for c in r.selected_per_level[:r.levels_run]]
+        assert n[0] == w["divisions"] ** D
+        assert r.n_samples == sum(n) * w["trials"] * w["samples"]
+        for l in range(r.levels_run):
+            assert sel[l] <= math.floor(n[l] / (1 + w["sigma_mult"] ** 2))
+            if l + 1 < r.levels_run:
+                assert n[l + 1] == sel[l] * 2 ** D <= w["max_cubes_per_level"]
+        if r.flags & 1:
+            assert sel[r.levels_run - 1] * 2 ** D > w["max_cubes_per_level"]
+    # per family, two integrals the oracle can run in about a second
+    # (300..3000 cubes in all), refined ones first
+    picks = []
+    for fam in W.GENZ_FAMILIES:
+        idx = [i for i, w in enumerate(ws) if w["integrand"] == fam and 300 <= outs[i].n_cubes <= 3000]
+        idx.sort(key=lambda i: (-outs[i].levels_run, outs[i].n_cubes))
+        picks += idx[:2]
+    assert len(picks) >= 6
+    for i in picks:
+        w = ws[i]
+        print("batch 4096: integral %d alone (family %d, D=%d, %d cubes)" % (
+            i, w["integrand"], len(w["lower"]), outs[i].n_cubes), flush=True)
+        ra = z.integrate(**w, trace=True)
+        assert ra.integral == outs[i].integral and ra.std == outs[i].std
+        compare_tree(orc, w, ra, 1e-4, 1e-4)
 
 
 def test_paper_f2_split_readings(zi):
