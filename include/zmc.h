@@ -105,6 +105,8 @@ typedef enum { ZMC_EVAL_FP64 = 0, ZMC_EVAL_FP32 = 1 } zmc_eval;
                              the cubes selected there were accepted instead */
 #define ZMC_F_RTOL_MET 2  /* the search stopped because stderr <= rtol*|I|  */
 
+/* Result of one integration.  integral, std and stderr_ are NaN unless
+ * status is ZMC_OK; the per-level fields cover the levels that ran. */
 typedef struct {
     double integral;   /* sum of accepted per-cube means                     */
     double std;        /* sqrt(sum of accepted s^2)                          */
@@ -222,7 +224,10 @@ int zmc_integrate_request(const zmc_request* req, void* stream, zmc_result* out,
  * zmc_integrate_request() returns for that request alone.  Returns ZMC_OK if
  * the batch ran (per-request failures are in outs[i].status), EINVAL if n <
  * 1, n > max_slots or any request is invalid, ENOMEM if the arena cannot
- * hold the batch's first level. */
+ * hold the batch's first level.  A request whose worst-case tree (the level
+ * bound the serving admission uses) exceeds the whole arena is not run and
+ * gets status ENOMEM on its own; if the requests that do run exhaust the
+ * arena together, those still resident at that level get ENOMEM. */
 int zmc_integrate_batch(const zmc_request* reqs, int n, void* stream, zmc_result* outs);
 
 /* Serving (continuous batching at level granularity): enqueue a copy of req

@@ -266,6 +266,11 @@ void Engine::record_level(HostSlot& hs, const SegStats& S, int64_t n, double ms,
 void Engine::finish(HostSlot& hs)
 {
     zmc_result& R = hs.res;
+    if (R.status != ZMC_OK) {
+        // a failed or cancelled request has no estimate
+        R.integral = R.std = R.stderr_ = NAN;
+        return;
+    }
     R.integral = hs.totM;
     R.std = sqrt(hs.totS2);
     R.stderr_ = sqrt(hs.totS2 / (double)(hs.req.trials - 1));
@@ -683,6 +688,14 @@ int Engine::run(const zmc_request* reqs, int n, hipStream_t st, zmc_result* outs
                 hs.req = reqs[i];
                 init_result(hs.res);
                 hs.ticket = (uint64_t)i;
+                // in a batch, a request whose worst-case tree cannot fit the
+                // arena even alone fails by itself instead of taking the
+                // batch's shared levels down
+                if (n > 1 && reservation_bytes(reqs[i]) > budget_bytes()) {
+                    hs.res.status = ZMC_ENOMEM;
+                    outs[i] = hs.res;
+                    continue;
+                }
                 out.push_back(hs);
             }
             given = n;

@@ -180,25 +180,37 @@ int rtc_n_params(int id)
 }
 
 // The kernel for (id, D, eval) on the current device, compiled on first use.
+// The compiler runs outside the lock, so launches of kernels already built
+// never wait behind a compilation.
 static int rtc_get(int id, int dim, int eval, Compiled& out)
 {
-    std::lock_guard<std::mutex> lk(g_mu);
     const auto key = std::make_tuple(id, dim, eval);
-    auto it = g_cache.find(key);
-    if (it != g_cache.end()) {
-        out = it->second;
-        return ZMC_OK;
-    }
-    const int k = id - kUserBase;
-    if (k < 0 || k >= (int)g_defs.size()) {
-        set_error("unknown user integrand");
-        return ZMC_EINVAL;
+    std::string body;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_cache.find(key);
+        if (it != g_cache.end()) {
+            out = it->second;
+            return ZMC_OK;
+        }
+        const int k = id - kUserBase;
+        if (k < 0 || k >= (int)g_defs.size()) {
+            set_error("unknown user integrand");
+            return ZMC_EINVAL;
+        }
+        body = g_defs[k].body;
     }
     std::vector<char> code;
     std::string log;
-    if (compile(g_defs[k].body, dim, eval == ZMC_EVAL_FP32, code, log) != 0) {
+    if (compile(body, dim, eval == ZMC_EVAL_FP32, code, log) != 0) {
         set_error("user integrand does not compile:\n" + log);
         return ZMC_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_cache.find(key);
+    if (it != g_cache.end()) { // built meanwhile by another thread
+        out = it->second;
+        return ZMC_OK;
     }
     Compiled c;
     hipError_t e = hipModuleLoadData(&c.module, code.data());

@@ -50,6 +50,9 @@ CASES = {
     "split5_scope1_osc2d": lambda ev: _w(2, [0.25, 6.0, 9.0], 2, 0.0, 1.0, 4, 1500, 3, 0.0, 5, 1, ev),
     # ragged: split 7 on a 2-D corner peak, 49 children (not a tile multiple)
     "split7_cpeak2d": lambda ev: _w(4, [3.0, 2.0], 2, 0.0, 1.0, 2, 777, 3, 0.0, 7, 0, ev),
+    # degenerate per-parent case: one parent per level (levels of 16, 4, 4, 4
+    # cubes), so each level's only sibling group is the whole level
+    "scope1_single_parent": lambda ev: _w(0, [0.03, 1.0, 0.3, 0.3], 2, 0.0, 1.0, 4, 2000, 3, 1.0, 0, 1, ev),
 }
 
 
