@@ -34,8 +34,10 @@ struct Server {
     std::unordered_set<uint64_t> pending; // queued or resident
     std::unordered_set<uint64_t> cancelled;
     uint64_t next_ticket = 1;
-    volatile bool stop = false;
-    uint64_t n_completed = 0, n_levels = 0;
+    std::atomic<bool> stop{false};
+    bool exited = false; // the serving thread has returned (under mu)
+    uint64_t n_completed = 0;
+    std::atomic<uint64_t> n_levels{0};
     int resident = 0;
     int rc = ZMC_OK;
 };
@@ -250,14 +252,17 @@ void server_main(Server* S, int device)
     int rc = S->eng.drive(S->st, adm, nullptr, &S->stop, &S->n_levels);
     std::lock_guard<std::mutex> lk(S->mu);
     S->rc = rc;
-    // anything still queued ends cancelled
-    for (HostSlot& hs : S->queue) {
+    S->exited = true;
+    // every ticket not finished ends now: cancelled on shutdown, or with the
+    // error that stopped the serving thread (a device error leaves the
+    // resident requests unretired)
+    for (uint64_t t : S->pending) {
         zmc_result R;
         init_result(R);
-        R.status = ZMC_ECANCELED;
-        S->done[hs.ticket] = R;
-        S->pending.erase(hs.ticket);
+        R.status = rc != ZMC_OK ? rc : ZMC_ECANCELED;
+        S->done[t] = R;
     }
+    S->pending.clear();
     S->queue.clear();
     S->cv_done.notify_all();
 }
@@ -389,6 +394,7 @@ int zmc_submit(const zmc_request* req, uint64_t* ticket)
     hs.reserve = S->eng.reservation_bytes(*req);
     hs.t_submit = std::chrono::steady_clock::now();
     std::lock_guard<std::mutex> lk(S->mu);
+    if (S->exited) return fail(S->rc != ZMC_OK ? S->rc : ZMC_ENOINIT, "the serving thread has stopped");
     if (S->queue.size() >= S->queue_cap) return fail(ZMC_EBUSY, "request queue is full");
     hs.ticket = S->next_ticket++;
     S->pending.insert(hs.ticket);
@@ -449,7 +455,7 @@ int zmc_serve_stats(uint64_t out4[4])
     out4[0] = S->queue.size();
     out4[1] = (uint64_t)S->resident;
     out4[2] = S->n_completed;
-    out4[3] = S->n_levels;
+    out4[3] = S->n_levels.load(std::memory_order_relaxed);
     return ZMC_OK;
 }
 

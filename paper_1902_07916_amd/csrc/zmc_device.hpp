@@ -45,7 +45,7 @@ struct alignas(16) SlotDesc {
 struct alignas(16) Segment {
     int32_t slot, level;
     int64_t cube_base, n_cubes;
-    int64_t part_base;  // index of its first (cube, trial, chunk) partial
+    int64_t part_base;  // first of its partials, laid out [cube][trial * nch + chunk]
     int64_t tile_base;  // index of its first tile
     int64_t n_tiles;
     int64_t child_base; // where its children start in the next list

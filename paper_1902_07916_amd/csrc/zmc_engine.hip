@@ -549,8 +549,8 @@ int Engine::next_list(hipStream_t st, std::vector<LiveSeg>& live, const std::vec
 
 // ---------------------------------------------------------------------------
 // Shared level loop of run() and serving.
-int Engine::drive(hipStream_t st, Admission& adm, zmc_trace* trace, const volatile bool* stop_flag,
-                  uint64_t* levels_stepped)
+int Engine::drive(hipStream_t st, Admission& adm, zmc_trace* trace, const std::atomic<bool>* stop_flag,
+                  std::atomic<uint64_t>* levels_stepped)
 {
     std::vector<int> free_ids;
     for (int i = max_slots_ - 1; i >= 0; --i) free_ids.push_back(i);
@@ -569,7 +569,7 @@ int Engine::drive(hipStream_t st, Admission& adm, zmc_trace* trace, const volati
             const double t0 = now_ms();
             int rc = step(st, live, cur_uid, cur_side, trace, false, false);
             const double ms = now_ms() - t0;
-            if (levels_stepped) ++*levels_stepped;
+            if (levels_stepped) levels_stepped->fetch_add(1, std::memory_order_relaxed);
             for (size_t i = 0; i < live.size(); ++i) {
                 HostSlot& hs = slots_[live[i].slot];
                 bool done = true;
@@ -603,7 +603,7 @@ int Engine::drive(hipStream_t st, Admission& adm, zmc_trace* trace, const volati
                 if (rc == ZMC_EDEVICE) return rc;
             }
         }
-        if (stop_flag && *stop_flag) {
+        if (stop_flag && stop_flag->load(std::memory_order_acquire)) {
             // retire what is still resident
             for (size_t i = 0; i < live.size(); ++i)
                 if (split[i]) {

@@ -23,6 +23,7 @@
 #include <string>
 #include <thread>
 #include <unordered_map>
+#include <atomic>
 #include <vector>
 
 #include "zmc.h"
@@ -126,8 +127,8 @@ public:
         std::function<void(HostSlot& done)> retire;
         std::function<bool(uint64_t ticket)> cancelled;
     };
-    int drive(hipStream_t st, Admission& adm, zmc_trace* trace, const volatile bool* stop_flag,
-              uint64_t* levels_stepped);
+    int drive(hipStream_t st, Admission& adm, zmc_trace* trace, const std::atomic<bool>* stop_flag,
+              std::atomic<uint64_t>* levels_stepped);
 
     size_t reservation_bytes(const zmc_request& r) const;
     size_t budget_bytes() const { return arena_.size(); }

@@ -85,6 +85,47 @@ __device__ int64_t block_sum_i(int64_t v, int64_t* sh)
     return t;
 }
 
+// The selection totals of a tile or a segment, reduced over the block in one
+// exchange: four sums, a minimum and a count, each combined in the same
+// fixed order as block_sum / block_min / block_sum_i.
+struct SelTotals {
+    double accM, accS2, selM, selS2, margin;
+    int64_t nsel;
+};
+
+__device__ SelTotals block_reduce_sel(SelTotals v)
+{
+    __shared__ double shd[kWaves][5];
+    __shared__ int64_t shn[kWaves];
+    v.accM = wave_sum(v.accM);
+    v.accS2 = wave_sum(v.accS2);
+    v.selM = wave_sum(v.selM);
+    v.selS2 = wave_sum(v.selS2);
+    v.margin = wave_min(v.margin);
+    v.nsel = wave_sum_i(v.nsel);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        const int w = threadIdx.x >> 6;
+        shd[w][0] = v.accM;
+        shd[w][1] = v.accS2;
+        shd[w][2] = v.selM;
+        shd[w][3] = v.selS2;
+        shd[w][4] = v.margin;
+        shn[w] = v.nsel;
+    }
+    __syncthreads();
+    SelTotals t{shd[0][0], shd[0][1], shd[0][2], shd[0][3], shd[0][4], 0};
+    for (int w = 1; w < kWaves; ++w) {
+        t.accM += shd[w][0];
+        t.accS2 += shd[w][1];
+        t.selM += shd[w][2];
+        t.selS2 += shd[w][3];
+        t.margin = fmin(t.margin, shd[w][4]);
+    }
+    for (int w = 0; w < kWaves; ++w) t.nsel += shn[w];
+    return t;
+}
+
 // Exclusive prefix of a 0/1 flag over the block in thread order; *total gets
 // the block's count.
 __device__ int block_excl_scan_flag(int flag, int* sh, int* total)
@@ -164,24 +205,45 @@ __device__ void seg_thr(const LevelArgs& a, int si)
 __device__ void seg_decide(const LevelArgs& a, int si);
 
 // ---- finalize: per cube I_t = V * S1_t / N, m = mean I_t, s = std I_t ------
+// The partial sums of 256 consecutive cubes are contiguous ([cube][trial *
+// nch + chunk]); when they fit kStage pairs, the block first copies them to
+// LDS with coalesced loads, and each thread then reads its own cube's row
+// there.  Larger rows (many trials or chunks) are read from memory directly.
+constexpr int kStage = 2560; // 40 KiB of (S1, S2) pairs
+
 __global__ __launch_bounds__(kLevelThreads) void finalize_kernel(const LevelArgs a)
 {
     __shared__ double sh[kWaves];
+    __shared__ double2 stage[kStage];
     const int64_t tile = blockIdx.x;
     const int si = seg_of_tile(a.segs, a.n_segs, tile);
     const Segment& sg = a.segs[si];
     const SlotDesc& sd = a.slots[sg.slot];
     const int D = sd.dim, n1 = sd.trials, nch = sd.nch;
+    const int per = n1 * nch; // pairs per cube
+    const bool staged = per * kLevelThreads <= kStage;
     const double V = cube_volume(sd, D, sg.level);
     const double N = (double)sd.samples;
     const int64_t first = (tile - sg.tile_base) * kTileCubes;
     double sum_s = 0.0;
     int bad = 0;
     for (int j = 0; j < kPerThread; ++j) {
-        const int64_t cl = first + threadIdx.x + (int64_t)j * kLevelThreads;
-        if (cl >= sg.n_cubes) break;
+        const int64_t c0 = first + (int64_t)j * kLevelThreads; // first cube of this pass
+        if (c0 >= sg.n_cubes) break;                            // uniform over the block
+        const int cnt = (int)min<int64_t>(kLevelThreads, sg.n_cubes - c0);
+        const double2* P;
+        if (staged) {
+            const double2* src = a.partial + sg.part_base + c0 * per;
+            __syncthreads(); // the previous pass is done with the stage
+            for (int e = threadIdx.x; e < cnt * per; e += kLevelThreads) stage[e] = src[e];
+            __syncthreads();
+            P = stage + threadIdx.x * per;
+        } else {
+            P = a.partial + sg.part_base + (c0 + threadIdx.x) * per;
+        }
+        if ((int)threadIdx.x >= cnt) continue;
+        const int64_t cl = c0 + threadIdx.x;
         const int64_t c = sg.cube_base + cl;
-        const double2* P = a.partial + sg.part_base + cl * (int64_t)n1 * nch;
         double sum = 0.0;
         for (int t = 0; t < n1; ++t) {
             double S1 = 0.0, S2 = 0.0;
@@ -281,8 +343,6 @@ __global__ __launch_bounds__(kLevelThreads) void group_thr_kernel(const LevelArg
 // ---- selection: split = s > thr; accepted and selected sums per tile -------
 __global__ __launch_bounds__(kLevelThreads) void tile_select_kernel(const LevelArgs a)
 {
-    __shared__ double sh[kWaves];
-    __shared__ int64_t shi[kWaves];
     const int64_t tile = blockIdx.x;
     const int si = seg_of_tile(a.segs, a.n_segs, tile);
     const Segment& sg = a.segs[si];
@@ -309,20 +369,15 @@ __global__ __launch_bounds__(kLevelThreads) void tile_select_kernel(const LevelA
         }
         if (thr_on && thr > 0.0) margin = fmin(margin, fabs(s - thr) / thr);
     }
-    const double tAccM = block_sum(accM, sh);
-    const double tAccS2 = block_sum(accS2, sh);
-    const double tSelM = block_sum(selM, sh);
-    const double tSelS2 = block_sum(selS2, sh);
-    const double tMargin = block_min(margin, sh);
-    const int64_t tSel = block_sum_i(nsel, shi);
+    const SelTotals tot = block_reduce_sel(SelTotals{accM, accS2, selM, selS2, margin, nsel});
     if (threadIdx.x == 0) {
         TileRec& T = a.tiles[tile];
-        T.accM = tAccM;
-        T.accS2 = tAccS2;
-        T.selM = tSelM;
-        T.selS2 = tSelS2;
-        T.min_margin = tMargin;
-        T.n_sel = tSel;
+        T.accM = tot.accM;
+        T.accS2 = tot.accS2;
+        T.selM = tot.selM;
+        T.selS2 = tot.selS2;
+        T.min_margin = tot.margin;
+        T.n_sel = tot.nsel;
     }
     if (last_tile_of_segment(a.seg_count, si, sg.n_tiles)) seg_decide(a, si);
 }
@@ -330,7 +385,6 @@ __global__ __launch_bounds__(kLevelThreads) void tile_select_kernel(const LevelA
 // ---- per segment: totals, stop rules, rank base of every tile --------------
 __device__ void seg_decide(const LevelArgs& a, int si)
 {
-    __shared__ double sh[kWaves];
     __shared__ int64_t shi[kWaves];
     const Segment& sg = a.segs[si];
     const SlotDesc& sd = a.slots[sg.slot];
@@ -347,12 +401,15 @@ __device__ void seg_decide(const LevelArgs& a, int si)
         nsel += T.n_sel;
         bad |= T.nonfinite;
     }
-    accM = block_sum(accM, sh);
-    accS2 = block_sum(accS2, sh);
-    selM = block_sum(selM, sh);
-    selS2 = block_sum(selS2, sh);
-    margin = block_min(margin, sh);
-    nsel = block_sum_i(nsel, shi);
+    {
+        const SelTotals tot = block_reduce_sel(SelTotals{accM, accS2, selM, selS2, margin, nsel});
+        accM = tot.accM;
+        accS2 = tot.accS2;
+        selM = tot.selM;
+        selS2 = tot.selS2;
+        margin = tot.margin;
+        nsel = tot.nsel;
+    }
     bad = __syncthreads_or(bad);
 
     // exclusive prefix of the tiles' selection counts (rank base for spawn)

@@ -205,6 +205,8 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
 
         S1 = wave_sum(S1);
         S2 = wave_sum(S2);
+        // partial sums in unit order, [cube][trial * nch + chunk]: a wave's
+        // consecutive units fill whole cache lines
         if (lane == 0) a.partial[sg.part_base + local] = make_double2(S1, S2);
     }
 }
