@@ -85,9 +85,10 @@ WORKLOADS = {
 }
 
 
+# The files the sampling kernel's code comes from (the level kernels'
+# arguments and launchers in zmc_kernels.hpp do not enter it).
 KERNEL_SOURCES = ("paper_1902_07916_amd/csrc/zmc_sample.hip", "paper_1902_07916_amd/csrc/zmc_sample_core.hpp",
-                  "paper_1902_07916_amd/csrc/zmc_integrands.hpp", "paper_1902_07916_amd/csrc/zmc_device.hpp",
-                  "paper_1902_07916_amd/csrc/zmc_kernels.hpp")
+                  "paper_1902_07916_amd/csrc/zmc_integrands.hpp", "paper_1902_07916_amd/csrc/zmc_device.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sample_kernel.json")
 
 

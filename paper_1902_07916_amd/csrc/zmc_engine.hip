@@ -36,6 +36,11 @@ int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// Levels of at most this many tiles run the per-segment steps in the tile
+// kernels' last blocks; larger ones launch them separately (each fused block
+// pays an L2 write-back to publish its tile record).
+constexpr int64_t kFuseMaxTiles = 256;
+
 // Packed per-level tables: segments at 0, running totals, bucket segments.
 size_t prev_offset(int ns) { return align256((size_t)ns * sizeof(Segment)); }
 size_t bseg_offset(int ns) { return prev_offset(ns) + align256((size_t)ns * sizeof(double2)); }
@@ -434,6 +439,8 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
     la.n_groups = groups;
     la.seg_count = d_seg_count_;
     la.host_stats = stats_only ? nullptr : d_hstats_;
+    // small levels fold the per-segment steps into the tile kernels
+    la.fused = tile <= kFuseMaxTiles ? 1 : 0;
     ZMC_HIP(launch_finalize(la, st));
     if (!stats_only) {
         if (any_thr) ZMC_HIP(launch_threshold(la, st));

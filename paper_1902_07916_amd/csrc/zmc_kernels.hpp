@@ -24,7 +24,7 @@ struct LevelArgs {
     const SlotDesc* slots;
     const Segment* segs;
     int32_t n_segs;
-    int32_t pad;
+    int32_t fused;           // per-segment steps in the tile kernels' last blocks
     int64_t n_tiles;
     const uint64_t* uid;
     const double2* partial;

@@ -7,10 +7,13 @@
 // per-cube kernels work on tiles of 1024 consecutive cubes of one segment
 // (256 threads, 4 cubes each, strided so that loads coalesce).  The
 // per-integral step that follows each of them (the mean of s, the threshold,
-// the decision) runs in the same launch: the last tile block of a segment to
-// finish, found with a per-segment counter, reduces that segment's tile
-// records in tile order.  A level therefore costs three short launches after
-// sampling.  Every reduction has a fixed shape (thread-serial over its
+// the decision) runs, for small levels, in the same launch: the last tile
+// block of a segment to finish, found with a per-segment counter, reduces
+// that segment's tile records in tile order, so a level costs three short
+// launches after sampling.  Publishing a tile record to the other XCDs takes
+// an L2 write-back per block, which outweighs a launch once a level has a few
+// hundred tiles; large levels therefore run the per-segment steps as their own
+// one-block-per-segment launches.  Every reduction has a fixed shape (thread-serial over its
 // elements, then wave64 butterflies, then the 4 waves in order), so results
 // are bitwise reproducible and independent of which block finishes last or
 // of what else is resident.
@@ -278,7 +281,8 @@ __global__ __launch_bounds__(kLevelThreads) void finalize_kernel(const LevelArgs
         a.tiles[tile].sum_s = tot;
         a.tiles[tile].nonfinite = any_bad;
     }
-    if (sg.need_thr && !sg.group_size && last_tile_of_segment(a.seg_count, si, sg.n_tiles)) seg_mean(a, si);
+    if (a.fused && sg.need_thr && !sg.group_size && last_tile_of_segment(a.seg_count, si, sg.n_tiles))
+        seg_mean(a, si);
 }
 
 // ---- threshold: std of s around the mean, per segment ----------------------
@@ -300,7 +304,22 @@ __global__ __launch_bounds__(kLevelThreads) void tile_sqdev_kernel(const LevelAr
     }
     const double tot = block_sum(acc, sh);
     if (threadIdx.x == 0) a.tiles[tile].sum_sq = tot;
-    if (last_tile_of_segment(a.seg_count, si, sg.n_tiles)) seg_thr(a, si);
+    if (a.fused && last_tile_of_segment(a.seg_count, si, sg.n_tiles)) seg_thr(a, si);
+}
+
+// ---- per-segment steps as their own launches (large levels) -----------------
+__global__ __launch_bounds__(kLevelThreads) void seg_mean_kernel(const LevelArgs a)
+{
+    const Segment& sg = a.segs[blockIdx.x];
+    if (!sg.need_thr || sg.group_size) return;
+    seg_mean(a, blockIdx.x);
+}
+
+__global__ __launch_bounds__(kLevelThreads) void seg_thr_kernel(const LevelArgs a)
+{
+    const Segment& sg = a.segs[blockIdx.x];
+    if (!sg.need_thr || sg.group_size) return;
+    seg_thr(a, blockIdx.x);
 }
 
 // ---- per-parent thresholds: one per group of siblings -----------------------
@@ -379,7 +398,7 @@ __global__ __launch_bounds__(kLevelThreads) void tile_select_kernel(const LevelA
         T.min_margin = tot.margin;
         T.n_sel = tot.nsel;
     }
-    if (last_tile_of_segment(a.seg_count, si, sg.n_tiles)) seg_decide(a, si);
+    if (a.fused && last_tile_of_segment(a.seg_count, si, sg.n_tiles)) seg_decide(a, si);
 }
 
 // ---- per segment: totals, stop rules, rank base of every tile --------------
@@ -479,6 +498,8 @@ __device__ void seg_decide(const LevelArgs& a, int si)
     }
 }
 
+__global__ __launch_bounds__(kLevelThreads) void seg_decide_kernel(const LevelArgs a) { seg_decide(a, blockIdx.x); }
+
 // ---- spawn: children of the selected cubes, in list order ------------------
 __global__ __launch_bounds__(kLevelThreads) void spawn_kernel(const LevelArgs a)
 {
@@ -573,7 +594,9 @@ hipError_t launch_finalize(const LevelArgs& a, hipStream_t st)
 hipError_t launch_threshold(const LevelArgs& a, hipStream_t st)
 {
     if (a.n_tiles <= 0) return hipSuccess;
+    if (!a.fused) hipLaunchKernelGGL(seg_mean_kernel, dim3(a.n_segs), dim3(kLevelThreads), 0, st, a);
     hipLaunchKernelGGL(tile_sqdev_kernel, dim3((unsigned)a.n_tiles), dim3(kLevelThreads), 0, st, a);
+    if (!a.fused) hipLaunchKernelGGL(seg_thr_kernel, dim3(a.n_segs), dim3(kLevelThreads), 0, st, a);
     return hipGetLastError();
 }
 
@@ -589,6 +612,7 @@ hipError_t launch_select(const LevelArgs& a, hipStream_t st)
 {
     if (a.n_tiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(tile_select_kernel, dim3((unsigned)a.n_tiles), dim3(kLevelThreads), 0, st, a);
+    if (!a.fused) hipLaunchKernelGGL(seg_decide_kernel, dim3(a.n_segs), dim3(kLevelThreads), 0, st, a);
     return hipGetLastError();
 }
 
