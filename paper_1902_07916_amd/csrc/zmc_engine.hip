@@ -46,6 +46,16 @@ size_t prev_offset(int ns) { return align256((size_t)ns * sizeof(Segment)); }
 size_t bseg_offset(int ns) { return prev_offset(ns) + align256((size_t)ns * sizeof(double2)); }
 size_t table_bytes(int max_segs) { return bseg_offset(max_segs) + (size_t)max_segs * sizeof(BSeg); }
 
+// Built-in occupancy variant per bucket (index into kWaveHints), measured by
+// the tuner on gfx950 and embedded at build time; a tuning file overrides it.
+#include "zmc_tune_default.inc"
+
+int default_wave_hint(int f, int d, int e)
+{
+    if (f < 0 || f >= 8 || d < 1 || d > ZMC_MAX_DIM || e < 0 || e > 1) return 0;
+    return kDefaultWaveHint[f][d][e] < kNumWaveHints ? kDefaultWaveHint[f][d][e] : 0;
+}
+
 // parts per axis when a cube is split (0 in a request means bisection)
 int split_of(const zmc_request& r) { return r.split ? r.split : 2; }
 
@@ -70,11 +80,16 @@ TileTable::TileTable()
 {
     for (int f = 0; f < 8; ++f)
         for (int d = 0; d <= ZMC_MAX_DIM; ++d)
-            for (int e = 0; e < 2; ++e) groups[f][d][e] = kDefaultGroups;
+            for (int e = 0; e < 2; ++e) {
+                groups[f][d][e] = kDefaultGroups;
+                hint[f][d][e] = default_wave_hint(f, d, e);
+            }
 }
 
 // Tuning file: a JSON object whose keys "integrand:dim:eval" map to the
-// number of 4-point groups per thread per chunk, e.g. {"1:6:1": 8}.
+// number of 4-point groups per thread per chunk, e.g. {"1:6:1": 8}, and whose
+// keys "integrand:dim:eval:w" map to the minimum waves per SIMD of the
+// occupancy variant (one of kWaveHints), e.g. {"1:6:1:w": 8}.
 int TileTable::load(const char* path)
 {
     std::ifstream in(path);
@@ -87,14 +102,19 @@ int TileTable::load(const char* path)
         const size_t q = t.find('"', p + 1);
         if (q == std::string::npos) break;
         int f, d, e;
+        char w = 0;
         const std::string key = t.substr(p + 1, q - p - 1);
         p = q + 1;
-        if (sscanf(key.c_str(), "%d:%d:%d", &f, &d, &e) != 3) continue;
+        const int nf = sscanf(key.c_str(), "%d:%d:%d:%c", &f, &d, &e, &w);
+        if (nf < 3) continue;
         const size_t c = t.find(':', q);
         if (c == std::string::npos) break;
         const int g = atoi(t.c_str() + c + 1);
-        if (f >= 0 && f < 8 && d >= 1 && d <= ZMC_MAX_DIM && e >= 0 && e < 2 && g >= 1 && g <= 64)
-            groups[f][d][e] = g;
+        if (!(f >= 0 && f < 8 && d >= 1 && d <= ZMC_MAX_DIM && e >= 0 && e < 2)) continue;
+        if (nf == 3 && g >= 1 && g <= 64) groups[f][d][e] = g;
+        if (nf == 4 && w == 'w')
+            for (int h = 0; h < kNumWaveHints; ++h)
+                if (kWaveHints[h] == g) hint[f][d][e] = h;
     }
     return 0;
 }
@@ -182,11 +202,12 @@ int Engine::nch_of(const zmc_request& r) const
 
 int Engine::capacity(int integrand, int dim, int eval)
 {
-    const int key = integrand * 1000 + dim * 2 + eval;
+    const int hint = tiles_->waves(integrand, dim, eval);
+    const int key = (integrand * 1000 + dim * 2 + eval) * kNumWaveHints + hint;
     auto it = cap_cache_.find(key);
     if (it != cap_cache_.end()) return it->second;
     int nb = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sample_kernel_ptr(integrand, dim, eval),
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sample_kernel_ptr(integrand, dim, eval, hint),
                                                                 kSampleThreads, 0);
     if (e != hipSuccess || nb < 1) nb = 1;
     const int cap = nb * std::max(n_cu_, 1);
@@ -413,7 +434,8 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
         } else {
             const int64_t cap = capacity(L.integrand, L.dim, L.eval);
             const int grid = (int)std::min<int64_t>(L.units, cap);
-            ZMC_HIP(launch_sample(L.integrand, L.dim, L.eval, grid, st, a));
+            ZMC_HIP(launch_sample(L.integrand, L.dim, L.eval, tiles_->waves(L.integrand, L.dim, L.eval), grid, st,
+                                  a));
         }
         ++n_launch;
     }

@@ -67,17 +67,23 @@ private:
 };
 
 // Tile shape of the sampling kernel per (integrand, dim, eval): the cap on
-// 4-point groups per lane per chunk (default 32; a chunk is one wave's unit).  Fixed per build or
-// tuning file, never by the batch composition, so a request's result does
-// not depend on its company.
+// 4-point groups per lane per chunk (default 32; a chunk is one wave's unit)
+// and the occupancy variant.  Fixed per build or tuning file, never by the
+// batch composition, so a request's result does not depend on its company
+// (the occupancy variant does not change any arithmetic at all).
 struct TileTable {
     int groups[8][ZMC_MAX_DIM + 1][2];
+    int hint[8][ZMC_MAX_DIM + 1][2]; // index into kWaveHints
     TileTable();
     int load(const char* path); // 0 on success
     int get(int integrand, int dim, int eval) const
     {
         // run-time compiled user integrands use the default cap
         return (integrand >= 0 && integrand < 8) ? groups[integrand][dim][eval] : kDefaultGroups;
+    }
+    int waves(int integrand, int dim, int eval) const
+    {
+        return (integrand >= 0 && integrand < 8) ? hint[integrand][dim][eval] : 0;
     }
     static constexpr int kDefaultGroups = 32;
 };

@@ -51,8 +51,15 @@ struct RootArgs {
 };
 
 // Launchers; each returns the hipError_t of its launch.
-hipError_t launch_sample(int integrand, int dim, int eval, int grid, hipStream_t st, const SampleArgs& a);
-const void* sample_kernel_ptr(int integrand, int dim, int eval);
+// Occupancy variants of every sampling kernel: the minimum waves per SIMD
+// the register allocator must allow (1 = no constraint).  More resident waves
+// hide more of the Philox latency, until the registers they leave each wave
+// make the allocator spill; which variant wins depends on the bucket.
+constexpr int kWaveHints[] = {1, 5, 8};
+constexpr int kNumWaveHints = 3;
+
+hipError_t launch_sample(int integrand, int dim, int eval, int hint, int grid, hipStream_t st, const SampleArgs& a);
+const void* sample_kernel_ptr(int integrand, int dim, int eval, int hint);
 hipError_t launch_finalize(const LevelArgs& a, hipStream_t st);
 hipError_t launch_threshold(const LevelArgs& a, hipStream_t st);
 hipError_t launch_group_threshold(const LevelArgs& a, hipStream_t st);
@@ -66,8 +73,8 @@ hipError_t launch_debug_points(const SlotDesc* sd, int level, uint64_t uid, int 
 
 // Per-integrand launch tables (one translation unit per integrand).
 #define ZMC_DECLARE_SAMPLE(F)                                                                              \
-    hipError_t launch_sample_##F(int dim, int eval, int grid, hipStream_t st, const SampleArgs& a);        \
-    const void* sample_kernel_ptr_##F(int dim, int eval);
+    hipError_t launch_sample_##F(int dim, int eval, int hint, int grid, hipStream_t st, const SampleArgs& a); \
+    const void* sample_kernel_ptr_##F(int dim, int eval, int hint);
 ZMC_DECLARE_SAMPLE(0)
 ZMC_DECLARE_SAMPLE(1)
 ZMC_DECLARE_SAMPLE(2)

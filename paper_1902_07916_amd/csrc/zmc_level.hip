@@ -648,32 +648,32 @@ hipError_t launch_debug_points(const SlotDesc* sd, int level, uint64_t uid, int 
     return hipGetLastError();
 }
 
-hipError_t launch_sample(int integrand, int dim, int eval, int grid, hipStream_t st, const SampleArgs& a)
+hipError_t launch_sample(int integrand, int dim, int eval, int hint, int grid, hipStream_t st, const SampleArgs& a)
 {
     switch (integrand) {
-    case 0: return launch_sample_0(dim, eval, grid, st, a);
-    case 1: return launch_sample_1(dim, eval, grid, st, a);
-    case 2: return launch_sample_2(dim, eval, grid, st, a);
-    case 3: return launch_sample_3(dim, eval, grid, st, a);
-    case 4: return launch_sample_4(dim, eval, grid, st, a);
-    case 5: return launch_sample_5(dim, eval, grid, st, a);
-    case 6: return launch_sample_6(dim, eval, grid, st, a);
-    case 7: return launch_sample_7(dim, eval, grid, st, a);
+    case 0: return launch_sample_0(dim, eval, hint, grid, st, a);
+    case 1: return launch_sample_1(dim, eval, hint, grid, st, a);
+    case 2: return launch_sample_2(dim, eval, hint, grid, st, a);
+    case 3: return launch_sample_3(dim, eval, hint, grid, st, a);
+    case 4: return launch_sample_4(dim, eval, hint, grid, st, a);
+    case 5: return launch_sample_5(dim, eval, hint, grid, st, a);
+    case 6: return launch_sample_6(dim, eval, hint, grid, st, a);
+    case 7: return launch_sample_7(dim, eval, hint, grid, st, a);
     default: return hipErrorInvalidValue;
     }
 }
 
-const void* sample_kernel_ptr(int integrand, int dim, int eval)
+const void* sample_kernel_ptr(int integrand, int dim, int eval, int hint)
 {
     switch (integrand) {
-    case 0: return sample_kernel_ptr_0(dim, eval);
-    case 1: return sample_kernel_ptr_1(dim, eval);
-    case 2: return sample_kernel_ptr_2(dim, eval);
-    case 3: return sample_kernel_ptr_3(dim, eval);
-    case 4: return sample_kernel_ptr_4(dim, eval);
-    case 5: return sample_kernel_ptr_5(dim, eval);
-    case 6: return sample_kernel_ptr_6(dim, eval);
-    case 7: return sample_kernel_ptr_7(dim, eval);
+    case 0: return sample_kernel_ptr_0(dim, eval, hint);
+    case 1: return sample_kernel_ptr_1(dim, eval, hint);
+    case 2: return sample_kernel_ptr_2(dim, eval, hint);
+    case 3: return sample_kernel_ptr_3(dim, eval, hint);
+    case 4: return sample_kernel_ptr_4(dim, eval, hint);
+    case 5: return sample_kernel_ptr_5(dim, eval, hint);
+    case 6: return sample_kernel_ptr_6(dim, eval, hint);
+    case 7: return sample_kernel_ptr_7(dim, eval, hint);
     default: return nullptr;
     }
 }

@@ -1,6 +1,7 @@
 """Autotuner for the sampling kernel's tile shape.
 
     python -m paper_1902_07916_amd.tune --out tune.json [--dims 2-12] [--integrands genz_osc,...]
+    python -m paper_1902_07916_amd.tune --waves --out tune.json --dims 1-16 --evals fp32,fp64
 
 For every (integrand, D, eval) bucket it times the sampling + per-cube
 reduction of a fixed list of root cubes (zmc_cube_estimates, N points per
@@ -74,36 +75,88 @@ def time_bucket(name: str, D: int, eval_: str, groups: int, n_cubes: int = 4096,
         os.unlink(path)
 
 
-def rate_table(evals=("fp32", "fp64"), dims=(2, 4, 6, 9, 12, 16), n_target=65536, N=16384, trials=3):
-    """Sampling-kernel rate per bucket from HIP-event kernel time: one level
-    (max_depth 0) over d^D >= n_target root cubes of [0,1]^D."""
+REGISTRY = ("sin_sum", "gauss", "genz_osc", "genz_ppeak", "genz_cpeak", "genz_gauss")
+WAVE_HINTS = (1, 5, 8)  # the library's occupancy variants (minimum waves per SIMD)
+MIN_GAIN = 1.015        # a variant must beat the unconstrained kernel by 1.5% to be chosen
+
+
+def _bucket_rate(zi, name, D, ev, n_target, N, trials):
+    """Samples/s of the sampling launches (HIP events, best of 3) over one
+    level of d^D >= n_target root cubes of [0,1]^D."""
     import torch
-    from paper_1902_07916_amd import Integrator, make_request
+    from paper_1902_07916_amd import make_request
+    d = 2
+    while d ** D < n_target:
+        d += 1
+    req = make_request(name, _params(name, D), [0.0] * D, [1.0] * D, d, N, trials, 0, 1.0, 1, eval=ev)
+    zi.integrate_request(req)
+    torch.cuda.synchronize()
+    rs = [zi.integrate_request(req) for _ in range(3)]
+    ms = min(r.sample_ms_per_level[0] for r in rs)
+    return d ** D, rs[0].n_samples / (ms * 1e-3)
+
+
+def rate_table(evals=("fp32", "fp64"), dims=(2, 4, 6, 9, 12, 16), n_target=65536, N=16384, trials=3,
+               tune_path=None):
+    """Sampling-kernel rate per bucket from HIP-event kernel time, with the
+    fraction of the ALU roofline."""
+    from paper_1902_07916_amd import Integrator
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import bench
-    zi = Integrator(arena_bytes=16 << 30)
+    zi = Integrator(arena_bytes=16 << 30, tune_path=tune_path)
     rows = []
     for ev in evals:
-        for name in ("sin_sum", "gauss", "genz_osc", "genz_ppeak", "genz_cpeak", "genz_gauss"):
+        for name in REGISTRY:
             for D in dims:
                 if ev == "fp64" and D not in (4, 6, 9):
                     continue
-                d = 2
-                while d ** D < n_target:
-                    d += 1
-                req = make_request(name, _params(name, D), [0.0] * D, [1.0] * D, d, N, trials, 0, 1.0, 1, eval=ev)
-                zi.integrate_request(req)
-                torch.cuda.synchronize()
-                rs = [zi.integrate_request(req) for _ in range(3)]
-                ms = min(r.sample_ms_per_level[0] for r in rs)
-                sps = rs[0].n_samples / (ms * 1e-3)
+                cubes, sps = _bucket_rate(zi, name, D, ev, n_target, N, trials)
                 slots = bench.valu_slots_per_sample(name, D, ev)["total"]
                 frac = sps * slots / bench.VALU_PEAK
-                rows.append(dict(eval=ev, integrand=name, D=D, cubes=d ** D, samples_per_s=sps, frac=frac))
+                rows.append(dict(eval=ev, integrand=name, D=D, cubes=cubes, samples_per_s=sps, frac=frac))
                 print("%s %-11s D=%2d cubes=%7d %.3e samples/s  %5.1f%% of ALU roofline" % (
-                    ev, name, D, d ** D, sps, 100 * frac), flush=True)
+                    ev, name, D, cubes, sps, 100 * frac), flush=True)
     zi.close()
     return rows
+
+
+def wave_sweep(out_path, evals=("fp32", "fp64"), dims=range(1, 17), n_target=16384, N=16384, trials=3):
+    """Time every occupancy variant of every registry bucket and write the
+    fastest as {"integrand:dim:eval:w": waves} (merged into out_path)."""
+    from paper_1902_07916_amd import INTEGRANDS, Integrator
+    rates = {}
+    for w in WAVE_HINTS:
+        table = {"%d:%d:%d:w" % (INTEGRANDS[n], D, 1 if ev == "fp32" else 0): w
+                 for n in REGISTRY for D in dims for ev in evals}
+        with tempfile.NamedTemporaryFile("w", suffix=".json", delete=False) as fh:
+            json.dump(table, fh)
+            path = fh.name
+        try:
+            zi = Integrator(arena_bytes=16 << 30, tune_path=path)
+            for ev in evals:
+                for name in REGISTRY:
+                    for D in dims:
+                        rates[(name, D, ev, w)] = _bucket_rate(zi, name, D, ev, n_target, N, trials)[1]
+                        print("w%d %s %-11s D=%2d %.3e samples/s" % (w, ev, name, D, rates[(name, D, ev, w)]),
+                              flush=True)
+            zi.close()
+        finally:
+            os.unlink(path)
+    best = json.load(open(out_path)) if os.path.exists(out_path) else {}
+    for ev in evals:
+        for name in REGISTRY:
+            for D in dims:
+                r = {w: rates[(name, D, ev, w)] for w in WAVE_HINTS}
+                w_best = max(r, key=r.get)
+                if r[w_best] < MIN_GAIN * r[1]:
+                    w_best = 1  # within the timing noise: keep the unconstrained kernel
+                best["%d:%d:%d:w" % (INTEGRANDS[name], D, 1 if ev == "fp32" else 0)] = w_best
+                print("%s %-11s D=%2d  %s  best %d (%.1f%% over 1)" % (
+                    ev, name, D, " ".join("w%d:%.3e" % (w, v) for w, v in r.items()), w_best,
+                    100 * (r[w_best] / r[1] - 1)), flush=True)
+    with open(out_path, "w") as fh:
+        json.dump(best, fh, indent=1, sort_keys=True)
+    return best
 
 
 def main(argv=None) -> int:
@@ -114,9 +167,17 @@ def main(argv=None) -> int:
     ap.add_argument("--integrands", default="genz_osc,genz_ppeak,genz_cpeak,genz_gauss,gauss,sin_sum")
     ap.add_argument("--evals", default="fp32")
     ap.add_argument("--samples", type=int, default=16384, help="points per cube")
+    ap.add_argument("--waves", action="store_true",
+                    help="time every occupancy variant of every registry bucket; write the fastest to --out")
+    ap.add_argument("--tune-path", default=None, help="tuning file for --table")
     a = ap.parse_args(argv)
     if a.table:
-        rate_table(evals=a.evals.split(","), N=a.samples)
+        rate_table(evals=a.evals.split(","), N=a.samples, tune_path=a.tune_path)
+        return 0
+    if a.waves:
+        if not a.out:
+            ap.error("--waves needs --out")
+        wave_sweep(a.out, evals=a.evals.split(","), dims=_parse_dims(a.dims), N=a.samples)
         return 0
     if not a.out:
         ap.error("--out is required unless --table")
