@@ -25,54 +25,66 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # MI355X figures used by the roofline (vendor specification: 256 CUs at
-# 2.4 GHz; FP32 157.3 TFLOP/s = 128 FMA lanes per CU per clock).
+# 2.4 GHz; FP32 157.3 TFLOP/s = 128 FMA lanes per CU per clock, i.e. two
+# wave64 VALU instructions per SIMD every 4 clocks).
 N_CU = 256
 CLOCK_HZ = 2.4e9
-SLOTS_PER_CU_CLK = 128
-VALU_PEAK = N_CU * CLOCK_HZ * SLOTS_PER_CU_CLK   # 7.86e13 VALU slots/s
+ISSUE_LANES_PER_CU_CLK = 128
+VALU_PEAK = N_CU * CLOCK_HZ * ISSUE_LANES_PER_CU_CLK   # 7.86e13 VALU lane-instructions/s
+INT_LANES_PER_CU_CLK = 64   # one integer wave64 instruction per SIMD every 4 clocks (measured 52-66)
 FP32_PEAK_FLOPS = 157.3e12
 FP64_PEAK_FLOPS = 78.6e12
 
-# Issue cost in VALU slots (1 slot = one lane of the 128-lane/clock/CU FP32
-# rate) of each instruction class, from gfx950's issue rates: FP32
-# add/mul/FMA 128 lanes/clk/CU; 32-bit integer and bitwise ops, the 32x32->64
-# v_mad_u64_u32, FP64 ops and conversions 64; transcendentals (exp2, sin,
-# rcp) 32.  A throughput probe measured 107, 64, 53, 56 and 31 respectively.
-SLOT = dict(fp32=1.0, int=2.0, fp64=2.0, trans=4.0)
 
-
-def valu_slots_per_sample(integrand: str, D: int, eval_: str) -> dict:
-    """Minimal VALU slots per sample the method needs on this ISA.
+def valu_instructions_per_sample(integrand: str, D: int, eval_: str) -> dict:
+    """Minimal VALU instructions per sample the method needs on this ISA, by
+    class (each instruction counts once, whatever its width or pipe).
 
     RNG: D/4 Philox4x32-10 blocks per sample.  A block is 10 rounds of two
     32x32->64 products and two 3-input XORs; with counter words 1-3 uniform
     over a wave the first round's product of word 2, its XOR and the second
     round's product of word 0 are scalar work: 18 v_mad_u64_u32 + 19
-    v_bitop3_b32/v_xor_b32 per block.  Mapping: one v_alignbit_b32 per
-    coordinate plus the FMA that places it.  Integrand and the FP64
-    accumulation of f and f^2 per family."""
-    blocks = D / 4.0
-    rng = blocks * 37 * SLOT["int"]
+    v_bitop3_b32 per block.  Mapping: one v_alignbit_b32 per coordinate plus
+    the FMA that places it.  Integrand and the FP64 accumulation (convert,
+    add, FMA) per family."""
+    rng = D / 4.0 * 37
     if eval_ == "fp32":
-        mapping = D * (SLOT["int"] + SLOT["fp32"])
+        ints, fp32, fp64, trans = rng + D, float(D), 3.0, 0.0
         if integrand in ("sin_sum", "genz_osc"):
-            # + low part of the cube phase; r - rint(r), fold to [-1/4, 1/4]
-            # (cmp, copysign, sub, select), t^2, 6 FMA, *t
-            f = 8 * SLOT["fp32"] + 3 * SLOT["int"] + 2 * SLOT["fp32"]
+            # low part of the cube phase; r - rint(r), fold to [-1/4, 1/4]
+            # (compare, copysign, select), t^2, 6 FMA, *t
+            fp32 += 10
+            ints += 3
         elif integrand in ("gauss", "genz_gauss"):
-            f = D * SLOT["fp32"] + 2 * SLOT["fp32"] + SLOT["trans"]      # t^2 sum, scale, exp2, A*
+            fp32 += D + 2          # t^2 sum, scale, A *
+            trans += 1             # exp2
         elif integrand == "genz_ppeak":
-            f = 2 * D * SLOT["fp32"] + SLOT["trans"]
+            fp32 += 2 * D
+            trans += 1             # rcp
         else:
-            f = 5 * SLOT["fp32"] + SLOT["trans"]
-        acc = 3 * SLOT["fp64"]                                            # cvt, add, fma
+            fp32 += 5
+            trans += 1
         flops32 = 2 * D + 2 * D + 4
     else:
-        mapping = D * (2 * SLOT["int"] + 2 * SLOT["fp64"])               # shift|1, cvt, fma
-        f = D * SLOT["fp64"] + 30 * SLOT["fp64"]                         # sum + FP64 sin/exp
-        acc = 2 * SLOT["fp64"]
+        ints, fp32, fp64, trans = rng + D, 0.0, 2.0 * D, 0.0   # shift|1, cvt, fma per coordinate
+        fp64 += D + 30 + 2                                       # sum, FP64 sin/exp, accumulation
         flops32 = 0
-    return dict(rng=rng, map=mapping, f=f, acc=acc, total=rng + mapping + f + acc, fp32_flops=flops32)
+    total = ints + fp32 + fp64 + trans
+    return dict(rng=rng, int=ints, fp32=fp32, fp64=fp64, trans=trans, total=total, fp32_flops=flops32)
+
+
+def alu_roofline(samples_per_s: float, integrand: str, D: int, eval_: str) -> dict:
+    """Issue roofline: a CU issues at most 128 VALU lane-instructions per
+    clock, so samples/s <= 7.86e13 / instructions per sample.  Also the
+    integer-issue view: integer and FP64 instructions issue at about 64
+    lanes per CU per clock (no dual issue among them; measured 52-66)."""
+    n = valu_instructions_per_sample(integrand, D, eval_)
+    achieved = samples_per_s * n["total"]
+    int_rate = samples_per_s * (n["int"] + n["fp64"])
+    return dict(achieved=achieved, peak=VALU_PEAK, frac=achieved / VALU_PEAK, instructions_per_sample=n,
+                roofline_samples_per_s=VALU_PEAK / n["total"],
+                int_issue_frac=int_rate / (N_CU * CLOCK_HZ * INT_LANES_PER_CU_CLK),
+                int_bound_samples_per_s=N_CU * CLOCK_HZ * INT_LANES_PER_CU_CLK / (n["int"] + n["fp64"]))
 
 
 WORKLOADS = {
@@ -162,12 +174,12 @@ def run_batch(a) -> dict:
     zi.close()
     last = outs[-1]
     samples = sum(r.n_samples for o in outs for r in o)
-    # algorithmic VALU slots of the last step: every sample of every level
+    # minimal VALU instructions of the last step: every sample of every level
     names = {v: k for k, v in INTEGRANDS.items()}
-    slots = 0.0
+    instr = 0.0
     for w, r in zip(ws, last):
-        per = valu_slots_per_sample(names[w["integrand"]], len(w["lower"]), w["eval"])["total"]
-        slots += per * sum(int(c) for c in r.cubes_per_level[:r.levels_run]) * w["trials"] * w["samples"]
+        per = valu_instructions_per_sample(names[w["integrand"]], len(w["lower"]), w["eval"])["total"]
+        instr += per * sum(int(c) for c in r.cubes_per_level[:r.levels_run]) * w["trials"] * w["samples"]
     # sampling-kernel time of the last step: integrals stepped together
     # share one launch set per level, whose HIP-event time every one of them
     # records; count each (level, time) once
@@ -177,8 +189,8 @@ def run_batch(a) -> dict:
             "status_ok": sum(r.status == 0 for r in last), "truncated": sum(bool(r.flags & 1) for r in last),
             "cubes_total": sum(r.n_cubes for r in last), "samples_per_step": samples // a.steps,
             "sample_kernel_ms_per_step": k_ms,
-            "alu_frac_sampling": slots / (k_ms * 1e-3) / VALU_PEAK if k_ms > 0 else None,
-            "alu_frac_wall": slots / (dt / a.steps) / VALU_PEAK}
+            "alu_frac_sampling": instr / (k_ms * 1e-3) / VALU_PEAK if k_ms > 0 else None,
+            "alu_frac_wall": instr / (dt / a.steps) / VALU_PEAK}
 
 
 def run_serve(a) -> dict:
@@ -327,15 +339,16 @@ def main(argv=None) -> int:
     k_ms = sum(sum(x.sample_ms_per_level) for x in results)
     k_launches = sum(sum(x.sample_launches_per_level) for x in results)
     k_samples = samples
-    cyc = valu_slots_per_sample(integrand, D, "fp32")
-    achieved = k_samples * cyc["total"] / (k_ms * 1e-3)
-    roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK, "unit": "VALU slots/s",
-                "frac": achieved / VALU_PEAK, "traffic": measured_traffic(a.workload),
+    k_rate = k_samples / (k_ms * 1e-3)
+    rl = alu_roofline(k_rate, integrand, D, "fp32")
+    roofline = {"bound": "alu", "achieved": rl["achieved"], "peak": VALU_PEAK, "unit": "VALU lane-instructions/s",
+                "frac": rl["frac"], "traffic": measured_traffic(a.workload),
                 "kernel": "sample_kernel<%s,D=%d,FP32>" % (integrand, D),
                 "avg_launch_ms": k_ms / max(k_launches, 1), "launches": k_launches,
-                "slots_per_sample": cyc, "kernel_samples_per_s": k_samples / (k_ms * 1e-3),
-                "roofline_samples_per_s": VALU_PEAK / cyc["total"],
-                "fp32_flop_frac": k_samples * cyc["fp32_flops"] / (k_ms * 1e-3) / FP32_PEAK_FLOPS}
+                "instructions_per_sample": rl["instructions_per_sample"], "kernel_samples_per_s": k_rate,
+                "roofline_samples_per_s": rl["roofline_samples_per_s"],
+                "int_issue_frac": rl["int_issue_frac"], "int_bound_samples_per_s": rl["int_bound_samples_per_s"],
+                "fp32_flop_frac": k_rate * rl["instructions_per_sample"]["fp32_flops"] / FP32_PEAK_FLOPS}
 
     out = {"metric": "integrand samples/sec + % FP32 VALU peak vs plain FP64; p50/p99 latency at QPS",
            "value": value, "unit": "samples/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,

@@ -55,8 +55,8 @@ struct RootArgs {
 // the register allocator must allow (1 = no constraint).  More resident waves
 // hide more of the Philox latency, until the registers they leave each wave
 // make the allocator spill; which variant wins depends on the bucket.
-constexpr int kWaveHints[] = {1, 5, 8};
-constexpr int kNumWaveHints = 3;
+constexpr int kWaveHints[] = {1, 5, 7, 8};
+constexpr int kNumWaveHints = 4;
 
 hipError_t launch_sample(int integrand, int dim, int eval, int hint, int grid, hipStream_t st, const SampleArgs& a);
 const void* sample_kernel_ptr(int integrand, int dim, int eval, int hint);

@@ -24,10 +24,11 @@ __global__ __launch_bounds__(kSampleThreads) __attribute__((amdgpu_waves_per_eu(
 template <int F, int D, bool FP32>
 const void* ptr_dew(int hint)
 {
-    static_assert(kNumWaveHints == 3, "one case per occupancy variant");
+    static_assert(kNumWaveHints == 4, "one case per occupancy variant");
     switch (hint) {
     case 1: return (const void*)&sample_kernel<F, D, FP32, kWaveHints[1]>;
     case 2: return (const void*)&sample_kernel<F, D, FP32, kWaveHints[2]>;
+    case 3: return (const void*)&sample_kernel<F, D, FP32, kWaveHints[3]>;
     default: return (const void*)&sample_kernel<F, D, FP32, kWaveHints[0]>;
     }
 }

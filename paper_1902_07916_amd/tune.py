@@ -76,7 +76,7 @@ def time_bucket(name: str, D: int, eval_: str, groups: int, n_cubes: int = 4096,
 
 
 REGISTRY = ("sin_sum", "gauss", "genz_osc", "genz_ppeak", "genz_cpeak", "genz_gauss")
-WAVE_HINTS = (1, 5, 8)  # the library's occupancy variants (minimum waves per SIMD)
+WAVE_HINTS = (1, 5, 7, 8)  # the library's occupancy variants (minimum waves per SIMD)
 MIN_GAIN = 1.015        # a variant must beat the unconstrained kernel by 1.5% to be chosen
 
 
@@ -111,11 +111,12 @@ def rate_table(evals=("fp32", "fp64"), dims=(2, 4, 6, 9, 12, 16), n_target=65536
                 if ev == "fp64" and D not in (4, 6, 9):
                     continue
                 cubes, sps = _bucket_rate(zi, name, D, ev, n_target, N, trials)
-                slots = bench.valu_slots_per_sample(name, D, ev)["total"]
-                frac = sps * slots / bench.VALU_PEAK
-                rows.append(dict(eval=ev, integrand=name, D=D, cubes=cubes, samples_per_s=sps, frac=frac))
-                print("%s %-11s D=%2d cubes=%7d %.3e samples/s  %5.1f%% of ALU roofline" % (
-                    ev, name, D, cubes, sps, 100 * frac), flush=True)
+                rl = bench.alu_roofline(sps, name, D, ev)
+                rows.append(dict(eval=ev, integrand=name, D=D, cubes=cubes, samples_per_s=sps, frac=rl["frac"],
+                                 int_issue_frac=rl["int_issue_frac"]))
+                print("%s %-11s D=%2d cubes=%7d %.3e samples/s  %5.1f%% of the VALU issue roofline, %5.1f%% of "
+                      "integer issue" % (ev, name, D, cubes, sps, 100 * rl["frac"], 100 * rl["int_issue_frac"]),
+                      flush=True)
     zi.close()
     return rows
 
