@@ -292,7 +292,7 @@ def main(argv=None) -> int:
                     help="first copy a buffer of this size with a plain copy kernel (calibrates HBM byte counters)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the work would shard by whole "
+        print("bench.py measures one GPU: the library has no multi-GPU path (the work would shard by whole "
               "integrals or by contiguous uid ranges with one small all-reduce per level); run with --gpus 1",
               file=sys.stderr)
         return 2
