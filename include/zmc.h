@@ -169,6 +169,15 @@ typedef struct {
                                serving disabled                               */
     const char* tune_path;  /* JSON tile table written by the autotuner; NULL
                                or "" = built-in defaults                      */
+    int32_t serve_lanes;    /* serving lanes (engine + thread + stream each;
+                               lane 0 uses serve_stream, the others streams
+                               the library creates, each on a hardware queue
+                               of its own); 0 = default 2, max 8              */
+    int32_t reserved;
+    int64_t serve_chunk_samples; /* serving splits a level's sampling into
+                               launches of about this many samples, so that
+                               lanes share the device between launches;
+                               0 = default 2^31, -1 = one launch per level    */
 } zmc_config;
 
 /* Per-level trace of a synchronous integration (test and debugging hook).

@@ -130,15 +130,20 @@ class Result:
 class Integrator:
     """Owns the device arena (a torch uint8 tensor) and the library context.
 
-    arena_bytes: device memory for all levels of the trees; serve: start the
-    serving thread on its own stream (the arena is split 1/4 synchronous,
-    3/4 serving).  The library holds one context per process: opening an
-    Integrator closes the one open before it, whose calls then raise."""
+    arena_bytes: device memory for all levels of the trees; serve: start
+    serving (the arena is split 1/4 synchronous, 3/4 serving); serve_lanes:
+    serving lanes, each an engine with its own thread, stream and equal share
+    of the serving arena (0 = the library's default of 2);
+    serve_chunk_samples: samples per sampling launch in serving (0 = the
+    library's default, -1 = one launch per level).  The library holds
+    one context per process: opening an Integrator closes the one open before
+    it, whose calls then raise."""
 
     _active = None
 
     def __init__(self, arena_bytes: int = 4 << 30, serve: bool = False, max_slots: int = 0, queue_depth: int = 0,
-                 tune_path: str | None = None, device: int = 0):
+                 tune_path: str | None = None, device: int = 0, serve_lanes: int = 0,
+                 serve_chunk_samples: int = 0):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Integrator needs a ROCm GPU (torch.cuda.is_available() is False)")
@@ -153,6 +158,8 @@ class Integrator:
         cfg.max_slots = int(max_slots)
         cfg.queue_depth = int(queue_depth)
         cfg.serve_stream = self.serve_stream.cuda_stream if serve else None
+        cfg.serve_lanes = int(serve_lanes)
+        cfg.serve_chunk_samples = int(serve_chunk_samples)
         self._tune = tune_path.encode() if tune_path else None
         cfg.tune_path = self._tune
         if Integrator._active is not None and Integrator._active is not self:

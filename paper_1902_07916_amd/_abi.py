@@ -58,6 +58,7 @@ class Config(C.Structure):
     _fields_ = [
         ("arena", C.c_void_p), ("arena_bytes", C.c_uint64), ("max_slots", C.c_int32),
         ("queue_depth", C.c_int32), ("serve_stream", C.c_void_p), ("tune_path", C.c_char_p),
+        ("serve_lanes", C.c_int32), ("reserved", C.c_int32), ("serve_chunk_samples", C.c_int64),
     ]
 
 

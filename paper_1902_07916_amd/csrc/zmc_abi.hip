@@ -9,10 +9,12 @@
 #include <atomic>
 #include <condition_variable>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <thread>
 #include <unordered_map>
 #include <unordered_set>
+#include <vector>
 
 #include "zmc.h"
 #include "zmc_engine.hpp"
@@ -22,10 +24,21 @@ using namespace zmc;
 
 namespace {
 
-struct Server {
+// One serving lane: an engine (its own slot table and arena share), the
+// stream it launches on and the thread that drives it.  Lanes admit from one
+// queue at their own level boundaries, so a request that arrives while one
+// lane is in a long level starts on another at once; their sampling launches
+// use more blocks than fit at a time, so the GPU interleaves the lanes' work.
+struct Lane {
     Engine eng;
     hipStream_t st = nullptr;
+    bool own_stream = false;
     std::thread th;
+    double next_samples = 0.0; // the lane's next level, as of its last boundary (under Server::mu)
+};
+
+struct Server {
+    std::vector<std::unique_ptr<Lane>> lanes;
     std::mutex mu;
     std::condition_variable cv_q, cv_done;
     std::deque<HostSlot> queue;
@@ -35,12 +48,24 @@ struct Server {
     std::unordered_set<uint64_t> cancelled;
     uint64_t next_ticket = 1;
     std::atomic<bool> stop{false};
-    bool exited = false; // the serving thread has returned (under mu)
+    int running = 0;     // lanes whose thread has not returned (under mu)
+    bool exited = false; // every lane has returned (under mu)
     uint64_t n_completed = 0;
     std::atomic<uint64_t> n_levels{0};
     int resident = 0;
     int rc = ZMC_OK;
 };
+
+// Serving lanes cut a level's sampling into launches of about this many
+// samples (about 4 ms of device time for FP32 integrands).  A launch that fills the
+// device holds its resources until its last block is dispatched: a kernel on
+// another lane whose blocks need more registers or LDS than one retiring
+// block frees waits for the whole launch otherwise.
+constexpr int64_t kServeChunkSamples = int64_t(1) << 31;
+// A busy lane whose next level takes more samples than this leaves newly
+// arrived requests to a lighter lane: a request admitted there would wait for
+// the whole of each heavy level before its own next level.
+constexpr double kLightLevelSamples = 268435456.0; // 2^28
 
 struct Context {
     bool inited = false;
@@ -190,14 +215,19 @@ double now_ms()
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
-void server_main(Server* S, int device)
+void server_main(Server* S, Lane* L, int device)
 {
     (void)hipSetDevice(device);
     Engine::Admission adm;
-    adm.admit = [S](std::vector<HostSlot>& out, int free_slots, size_t budget, bool idle) {
+    adm.admit = [S, L](std::vector<HostSlot>& out, int free_slots, size_t budget, bool idle,
+                       double next_samples) {
         std::unique_lock<std::mutex> lk(S->mu);
+        L->next_samples = next_samples;
         if (idle) {
             while (S->queue.empty() && !S->stop) S->cv_q.wait_for(lk, std::chrono::milliseconds(20));
+        } else if (next_samples > kLightLevelSamples) {
+            for (auto& o : S->lanes)
+                if (o.get() != L && o->next_samples < next_samples) return !S->stop;
         }
         while (!S->queue.empty() && free_slots > 0) {
             HostSlot& hs = S->queue.front();
@@ -212,7 +242,7 @@ void server_main(Server* S, int device)
                 S->cv_done.notify_all();
                 continue;
             }
-            if (hs.reserve > S->eng.budget_bytes()) {
+            if (hs.reserve > L->eng.budget_bytes()) {
                 zmc_result R;
                 init_result(R);
                 R.status = ZMC_ENOMEM;
@@ -249,22 +279,47 @@ void server_main(Server* S, int device)
         std::lock_guard<std::mutex> lk(S->mu);
         return S->cancelled.count(t) > 0;
     };
-    int rc = S->eng.drive(S->st, adm, nullptr, &S->stop, &S->n_levels);
+    int rc = L->eng.drive(L->st, adm, nullptr, &S->stop, &S->n_levels);
     std::lock_guard<std::mutex> lk(S->mu);
-    S->rc = rc;
+    if (rc != ZMC_OK && S->rc == ZMC_OK) S->rc = rc;
+    if (rc != ZMC_OK) {
+        // a failed lane stops every lane: their requests end below
+        S->stop = true;
+        S->cv_q.notify_all();
+    }
+    if (--S->running > 0) return;
     S->exited = true;
     // every ticket not finished ends now: cancelled on shutdown, or with the
-    // error that stopped the serving thread (a device error leaves the
-    // resident requests unretired)
+    // error that stopped serving (a device error leaves the resident requests
+    // of its lane unretired)
     for (uint64_t t : S->pending) {
         zmc_result R;
         init_result(R);
-        R.status = rc != ZMC_OK ? rc : ZMC_ECANCELED;
+        R.status = S->rc != ZMC_OK ? S->rc : ZMC_ECANCELED;
         S->done[t] = R;
     }
     S->pending.clear();
     S->queue.clear();
     S->cv_done.notify_all();
+}
+
+// A stream of a serving lane.  The runtime maps ordinary streams onto a few
+// hardware queues and hands a new stream the least used one, which may be
+// the queue of another lane: launches on one queue run one after another.
+// A stream with a CU mask always gets a hardware queue of its own; the mask
+// enables every compute unit.  (Such a stream synchronises with the null
+// stream like any stream created without hipStreamNonBlocking.)
+hipError_t create_lane_stream(hipStream_t* st)
+{
+    int n_cu = 0;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n_cu > 0) {
+        std::vector<uint32_t> mask((n_cu + 31) / 32, 0xffffffffu);
+        if (n_cu % 32) mask.back() = (1u << (n_cu % 32)) - 1u;
+        if (hipExtStreamCreateWithCUMask(st, (uint32_t)mask.size(), mask.data()) == hipSuccess) return hipSuccess;
+    }
+    return hipStreamCreateWithFlags(st, hipStreamNonBlocking);
 }
 
 void stop_server()
@@ -276,8 +331,12 @@ void stop_server()
         S->stop = true;
         S->cv_q.notify_all();
     }
-    if (S->th.joinable()) S->th.join();
-    S->eng.teardown();
+    for (auto& L : S->lanes)
+        if (L->th.joinable()) L->th.join();
+    for (auto& L : S->lanes) {
+        L->eng.teardown();
+        if (L->own_stream) (void)hipStreamDestroy(L->st);
+    }
     delete S;
     g.server = nullptr;
 }
@@ -292,6 +351,8 @@ int zmc_init(const zmc_config* cfg)
     if (!cfg || !cfg->arena) return fail(ZMC_EINVAL, "zmc_init: NULL config or arena");
     if (cfg->arena_bytes < (64ull << 20)) return fail(ZMC_EINVAL, "zmc_init: arena must be >= 64 MiB");
     if (((uintptr_t)cfg->arena & 255) != 0) return fail(ZMC_EINVAL, "zmc_init: arena must be 256-byte aligned");
+    if (cfg->serve_lanes < 0 || cfg->serve_lanes > 8) return fail(ZMC_EINVAL, "zmc_init: serve_lanes must be in 0..8");
+    if (cfg->serve_chunk_samples < -1) return fail(ZMC_EINVAL, "zmc_init: serve_chunk_samples must be >= -1");
     if (g.inited) {
         stop_server();
         g.sync_eng.teardown();
@@ -310,17 +371,38 @@ int zmc_init(const zmc_config* cfg)
     int rc = g.sync_eng.setup(base, sync_bytes, slots, &g.tiles, g.device);
     if (rc != ZMC_OK) return rc;
     if (cfg->serve_stream) {
+        const int n_lanes = cfg->serve_lanes > 0 ? cfg->serve_lanes : 2;
         Server* S = new Server();
-        S->st = (hipStream_t)cfg->serve_stream;
         S->queue_cap = cfg->queue_depth > 0 ? (size_t)cfg->queue_depth : 65536;
-        rc = S->eng.setup(base + sync_bytes, bytes - sync_bytes, slots, &g.tiles, g.device);
+        const size_t lane_bytes = ((bytes - sync_bytes) / n_lanes) & ~(size_t)255;
+        for (int i = 0; i < n_lanes && rc == ZMC_OK; ++i) {
+            S->lanes.emplace_back(new Lane());
+            Lane* L = S->lanes.back().get();
+            if (i == 0) {
+                L->st = (hipStream_t)cfg->serve_stream;
+            } else if (create_lane_stream(&L->st) == hipSuccess) {
+                L->own_stream = true;
+            } else {
+                rc = fail(ZMC_EDEVICE, "zmc_init: cannot create a serving stream");
+                break;
+            }
+            rc = L->eng.setup(base + sync_bytes + i * lane_bytes, lane_bytes, slots, &g.tiles, g.device);
+            L->eng.set_chunk_samples(cfg->serve_chunk_samples == 0 ? kServeChunkSamples
+                                     : cfg->serve_chunk_samples < 0 ? 0
+                                                                    : cfg->serve_chunk_samples);
+        }
         if (rc != ZMC_OK) {
+            for (auto& L : S->lanes) {
+                L->eng.teardown();
+                if (L->own_stream) (void)hipStreamDestroy(L->st);
+            }
             delete S;
             g.sync_eng.teardown();
             return rc;
         }
         g.server = S;
-        S->th = std::thread(server_main, S, g.device);
+        S->running = n_lanes;
+        for (auto& L : S->lanes) L->th = std::thread(server_main, S, L.get(), g.device);
     }
     g.inited = true;
     return ZMC_OK;
@@ -391,7 +473,7 @@ int zmc_submit(const zmc_request* req, uint64_t* ticket)
     HostSlot hs;
     hs.req = *req;
     init_result(hs.res);
-    hs.reserve = S->eng.reservation_bytes(*req);
+    hs.reserve = S->lanes[0]->eng.reservation_bytes(*req);
     hs.t_submit = std::chrono::steady_clock::now();
     std::lock_guard<std::mutex> lk(S->mu);
     if (S->exited) return fail(S->rc != ZMC_OK ? S->rc : ZMC_ENOINIT, "the serving thread has stopped");

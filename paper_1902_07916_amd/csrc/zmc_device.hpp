@@ -84,7 +84,8 @@ struct SampleArgs {
     const BSeg* bsegs;
     int32_t n_bsegs;
     int32_t pad;
-    int64_t total_units;
+    int64_t unit0;       // first unit of this launch (units are numbered over the level's bucket)
+    int64_t total_units; // units of this launch
     const uint64_t* uid;
     double2* partial;
 };

@@ -392,7 +392,7 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
     int nb = 0;
     struct Launch {
         int off, count, integrand, dim, eval;
-        int64_t units;
+        int64_t units, unit_samples;
     };
     std::vector<Launch> launches;
     for (auto& kv : buckets) {
@@ -403,6 +403,7 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
         L.integrand = r0.integrand;
         L.dim = r0.dim;
         L.eval = r0.eval;
+        L.unit_samples = 256LL * groups_of(r0);
         int64_t u = 0;
         for (int i : kv.second) {
             const zmc_request& r = slots_[live[i].slot].req;
@@ -425,19 +426,25 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
         a.segs = d_segs_;
         a.bsegs = d_bsegs_ + L.off;
         a.n_bsegs = L.count;
-        a.total_units = L.units;
         a.uid = cur_uid;
         a.partial = partial;
-        if (L.integrand >= kUserBase) {
-            const int rc = rtc_launch(L.integrand, L.dim, L.eval, L.units, st, a);
-            if (rc != ZMC_OK) return rc;
-        } else {
-            const int64_t cap = capacity(L.integrand, L.dim, L.eval);
-            const int grid = (int)std::min<int64_t>(L.units, cap);
-            ZMC_HIP(launch_sample(L.integrand, L.dim, L.eval, tiles_->waves(L.integrand, L.dim, L.eval), grid, st,
-                                  a));
+        // one launch, or launches of at most chunk_samples_ samples each
+        int64_t chunk = L.units;
+        if (chunk_samples_ > 0) chunk = std::max<int64_t>(1, chunk_samples_ / L.unit_samples);
+        for (int64_t u0 = 0; u0 < L.units; u0 += chunk) {
+            a.unit0 = u0;
+            a.total_units = std::min(chunk, L.units - u0);
+            if (L.integrand >= kUserBase) {
+                const int rc = rtc_launch(L.integrand, L.dim, L.eval, st, a);
+                if (rc != ZMC_OK) return rc;
+            } else {
+                const int64_t cap = capacity(L.integrand, L.dim, L.eval);
+                const int grid = (int)std::min<int64_t>(a.total_units, cap);
+                ZMC_HIP(launch_sample(L.integrand, L.dim, L.eval, tiles_->waves(L.integrand, L.dim, L.eval), grid,
+                                      st, a));
+            }
+            ++n_launch;
         }
-        ++n_launch;
     }
     ZMC_HIP(hipEventRecord(ev_sample1_, st));
 
@@ -646,10 +653,16 @@ int Engine::drive(hipStream_t st, Admission& adm, zmc_trace* trace, const std::a
         // admission at the level boundary
         std::vector<HostSlot> incoming;
         bool idle = true;
-        for (int v : split) idle &= (v == 0);
+        double next_samples = 0.0; // samples of the next level before admission
+        for (size_t i = 0; i < split.size(); ++i) {
+            if (!split[i]) continue;
+            idle = false;
+            const zmc_request& r = slots_[live[i].slot].req;
+            next_samples += (double)h_stats_[i].n_sel * (double)kids_of(r) * (double)r.samples_per_cube * r.trials;
+        }
         if (more) {
             const size_t budget = arena_.size() > reserved ? arena_.size() - reserved : 0;
-            more = adm.admit(incoming, (int)free_ids.size(), budget, idle);
+            more = adm.admit(incoming, (int)free_ids.size(), budget, idle, next_samples);
         }
         std::vector<LiveSeg> fresh;
         for (HostSlot& in : incoming) {
@@ -710,7 +723,7 @@ int Engine::run(const zmc_request* reqs, int n, hipStream_t st, zmc_result* outs
     std::vector<int> id_of_slot(max_slots_, -1);
     int given = 0;
     Admission adm;
-    adm.admit = [&](std::vector<HostSlot>& out, int free_slots, size_t, bool) {
+    adm.admit = [&](std::vector<HostSlot>& out, int free_slots, size_t, bool, double) {
         if (given == 0) {
             for (int i = 0; i < n && i < free_slots; ++i) {
                 HostSlot hs;

@@ -129,7 +129,11 @@ public:
     // `admit` may hand over new requests (they join with their roots),
     // `retire` receives every finished request, `cancelled` is polled.
     struct Admission {
-        std::function<bool(std::vector<HostSlot>& out, int free_slots, size_t free_budget, bool idle)> admit;
+        // called at each level boundary; next_samples = samples the resident
+        // integrals take at the next level (0 when idle)
+        std::function<bool(std::vector<HostSlot>& out, int free_slots, size_t free_budget, bool idle,
+                           double next_samples)>
+            admit;
         std::function<void(HostSlot& done)> retire;
         std::function<bool(uint64_t ticket)> cancelled;
     };
@@ -138,6 +142,10 @@ public:
 
     size_t reservation_bytes(const zmc_request& r) const;
     size_t budget_bytes() const { return arena_.size(); }
+    // 0 (default): one sampling launch per bucket and level; > 0: launches
+    // of about this many samples each, so that a long level leaves the
+    // device to launches on other streams between them
+    void set_chunk_samples(int64_t n) { chunk_samples_ = n; }
     int nch_of(const zmc_request& r) const;
     int groups_of(const zmc_request& r) const;
 
@@ -181,6 +189,7 @@ private:
     DualStack arena_;
     std::vector<HostSlot> slots_;
     std::map<int, int> cap_cache_;
+    int64_t chunk_samples_ = 0;
     // arrays of the level last stepped (valid until its spawn is enqueued)
     uint64_t* cur_uid_ = nullptr;
     double* cur_m_ = nullptr;

@@ -230,12 +230,12 @@ static int rtc_get(int id, int dim, int eval, Compiled& out)
     return ZMC_OK;
 }
 
-int rtc_launch(int id, int dim, int eval, int64_t units, hipStream_t st, const SampleArgs& a)
+int rtc_launch(int id, int dim, int eval, hipStream_t st, const SampleArgs& a)
 {
     Compiled c;
     const int rc = rtc_get(id, dim, eval, c);
     if (rc != ZMC_OK) return rc;
-    const unsigned grid = (unsigned)std::min<int64_t>(units, c.capacity);
+    const unsigned grid = (unsigned)std::min<int64_t>(a.total_units, c.capacity);
     SampleArgs arg = a;
     void* params[] = {&arg};
     const hipError_t e = hipModuleLaunchKernel(c.fn, grid, 1, 1, kSampleThreads, 1, 1, 0, st, params, nullptr);

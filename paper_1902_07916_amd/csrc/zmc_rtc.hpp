@@ -16,7 +16,7 @@ int rtc_register(const char* body, int n_params, int* id);
 // n_params of a registered user integrand, -1 if unknown.
 int rtc_n_params(int id);
 // Launch the (id, dim, eval) sampling kernel (compiled on first use) over
-// `units` units with a persistent grid.
-int rtc_launch(int id, int dim, int eval, int64_t units, hipStream_t st, const SampleArgs& a);
+// the a.total_units units from a.unit0 on, with a persistent grid.
+int rtc_launch(int id, int dim, int eval, hipStream_t st, const SampleArgs& a);
 
 } // namespace zmc

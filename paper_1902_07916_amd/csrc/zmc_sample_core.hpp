@@ -106,8 +106,8 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
     const int64_t n_waves = (int64_t)gridDim.x * kWaves;
     const int64_t U = a.total_units;
     const int64_t per = (U + n_waves - 1) / n_waves;
-    int64_t u = wave * per;
-    const int64_t uend = min(U, u + per);
+    int64_t u = a.unit0 + wave * per;
+    const int64_t uend = min(a.unit0 + U, u + per);
     if (u >= uend) return;
 
     int bs = 0;

@@ -96,6 +96,13 @@ def test_init_rejects_bad_config(lib):
     cfg.arena_bytes = 1 << 30
     cfg.arena = 257
     assert lib.zmc_init(C.byref(cfg)) == _abi.EINVAL
+    cfg.arena = 256
+    for lanes in (-1, 9):
+        cfg.serve_lanes = lanes
+        assert lib.zmc_init(C.byref(cfg)) == _abi.EINVAL
+    cfg.serve_lanes = 0
+    cfg.serve_chunk_samples = -2
+    assert lib.zmc_init(C.byref(cfg)) == _abi.EINVAL
 
 
 def test_integrate_scalar_entry_checks(lib):
