@@ -45,11 +45,12 @@ def valu_instructions_per_sample(integrand: str, D: int, eval_: str) -> dict:
     over a wave the first round's product of word 2, its XOR and the second
     round's product of word 0 are scalar work: 18 v_mad_u64_u32 + 19
     v_bitop3_b32 per block.  Mapping: one v_alignbit_b32 per coordinate plus
-    the FMA that places it.  Integrand and the FP64 accumulation (convert,
-    add, FMA) per family."""
+    the FMA that places it.  Integrand and the FP64 accumulation of the sum
+    (convert, add) per family; the sum of squares is kept only on traced
+    levels and is not counted."""
     rng = D / 4.0 * 37
     if eval_ == "fp32":
-        ints, fp32, fp64, trans = rng + D, float(D), 3.0, 0.0
+        ints, fp32, fp64, trans = rng + D, float(D), 2.0, 0.0
         if integrand in ("sin_sum", "genz_osc"):
             # low part of the cube phase; r - rint(r), fold to [-1/4, 1/4]
             # (compare, copysign, select), t^2, 6 FMA, *t
@@ -67,7 +68,7 @@ def valu_instructions_per_sample(integrand: str, D: int, eval_: str) -> dict:
         flops32 = 2 * D + 2 * D + 4
     else:
         ints, fp32, fp64, trans = rng + D, 0.0, 2.0 * D, 0.0   # shift|1, cvt, fma per coordinate
-        fp64 += D + 30 + 2                                       # sum, FP64 sin/exp, accumulation
+        fp64 += D + 30 + 1                                       # sum, FP64 sin/exp, accumulation
         flops32 = 0
     total = ints + fp32 + fp64 + trans
     return dict(rng=rng, int=ints, fp32=fp32, fp64=fp64, trans=trans, total=total, fp32_flops=flops32)
@@ -97,10 +98,11 @@ WORKLOADS = {
 }
 
 
-# The files the sampling kernel's code comes from (the level kernels'
-# arguments and launchers in zmc_kernels.hpp do not enter it).
-KERNEL_SOURCES = ("paper_1902_07916_amd/csrc/zmc_sample.hip", "paper_1902_07916_amd/csrc/zmc_sample_core.hpp",
-                  "paper_1902_07916_amd/csrc/zmc_integrands.hpp", "paper_1902_07916_amd/csrc/zmc_device.hpp")
+# The files the sampling kernel's code comes from, with the build flags (the
+# level kernels' arguments and launchers in zmc_kernels.hpp do not enter it).
+KERNEL_SOURCES = ("paper_1902_07916_amd/build.py", "paper_1902_07916_amd/csrc/zmc_sample.hip",
+                  "paper_1902_07916_amd/csrc/zmc_sample_core.hpp", "paper_1902_07916_amd/csrc/zmc_integrands.hpp",
+                  "paper_1902_07916_amd/csrc/zmc_device.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sample_kernel.json")
 
 

@@ -200,10 +200,10 @@ int Engine::nch_of(const zmc_request& r) const
     return (int)ceil_div(r.samples_per_cube, chunk);
 }
 
-int Engine::capacity(int integrand, int dim, int eval)
+int Engine::capacity(int integrand, int dim, int eval, bool keep_s2)
 {
-    const int hint = tiles_->waves(integrand, dim, eval);
-    const int key = (integrand * 1000 + dim * 2 + eval) * kNumWaveHints + hint;
+    const int hint = keep_s2 ? kSumsVariant : tiles_->waves(integrand, dim, eval);
+    const int key = (integrand * 1000 + dim * 2 + eval) * (kNumWaveHints + 1) + hint;
     auto it = cap_cache_.find(key);
     if (it != cap_cache_.end()) return it->second;
     int nb = 0;
@@ -438,10 +438,10 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
                 const int rc = rtc_launch(L.integrand, L.dim, L.eval, st, a);
                 if (rc != ZMC_OK) return rc;
             } else {
-                const int64_t cap = capacity(L.integrand, L.dim, L.eval);
+                const int64_t cap = capacity(L.integrand, L.dim, L.eval, sums);
                 const int grid = (int)std::min<int64_t>(a.total_units, cap);
-                ZMC_HIP(launch_sample(L.integrand, L.dim, L.eval, tiles_->waves(L.integrand, L.dim, L.eval), grid,
-                                      st, a));
+                const int hint = sums ? kSumsVariant : tiles_->waves(L.integrand, L.dim, L.eval);
+                ZMC_HIP(launch_sample(L.integrand, L.dim, L.eval, hint, grid, st, a));
             }
             ++n_launch;
         }

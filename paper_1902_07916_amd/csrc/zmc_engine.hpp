@@ -155,7 +155,7 @@ private:
              bool stats_only, bool want_sums);
     int next_list(hipStream_t st, std::vector<LiveSeg>& live, const std::vector<int>& split,
                   const std::vector<LiveSeg>& fresh, uint64_t*& cur_uid, int& cur_side);
-    int capacity(int integrand, int dim, int eval);
+    int capacity(int integrand, int dim, int eval, bool keep_s2);
     void record_level(HostSlot& hs, const SegStats& S, int64_t n, double ms, float sample_ms, int launches);
     void finish(HostSlot& hs);
 

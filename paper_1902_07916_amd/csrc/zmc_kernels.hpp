@@ -57,6 +57,9 @@ struct RootArgs {
 // make the allocator spill; which variant wins depends on the bucket.
 constexpr int kWaveHints[] = {1, 5, 7, 8};
 constexpr int kNumWaveHints = 4;
+// hint value that selects the sampling kernel that also keeps the sums of
+// squares (traced levels); it runs at the compiler's default occupancy
+constexpr int kSumsVariant = kNumWaveHints;
 
 hipError_t launch_sample(int integrand, int dim, int eval, int hint, int grid, hipStream_t st, const SampleArgs& a);
 const void* sample_kernel_ptr(int integrand, int dim, int eval, int hint);

@@ -105,7 +105,7 @@ struct UserIntegrand {
 } // namespace zmc
 extern "C" __global__ __launch_bounds__(256) void zmc_user_kernel(const zmc::SampleArgs a)
 {
-    zmc::sample_units<zmc::UserIntegrand<ZMC_D>, ZMC_D, ZMC_FP32>(a);
+    zmc::sample_units<zmc::UserIntegrand<ZMC_D>, ZMC_D, ZMC_FP32, true>(a);
 }
 )ZMCRTC";
     return s;

@@ -1,7 +1,7 @@
 // zmc_sample.hip -- the precompiled sampling kernels: one translation unit
 // per registry integrand (-DZMC_F=<id>), each instantiating D = 1..16 in FP64
-// and FP32 evaluation, in every occupancy variant, around the shared body in
-// zmc_sample_core.hpp.
+// and FP32 evaluation, in every occupancy variant and in the variant that
+// keeps sums of squares, around the shared body in zmc_sample_core.hpp.
 #include "zmc_integrands.hpp"
 #include "zmc_kernels.hpp"
 #include "zmc_sample_core.hpp"
@@ -18,7 +18,14 @@ template <int F, int D, bool FP32, int W>
 __global__ __launch_bounds__(kSampleThreads) __attribute__((amdgpu_waves_per_eu(W))) void sample_kernel(
     const SampleArgs a)
 {
-    sample_units<Integrand<F, D>, D, FP32>(a);
+    sample_units<Integrand<F, D>, D, FP32, false>(a);
+}
+
+// the variant that also keeps the sums of squares, for traced levels
+template <int F, int D, bool FP32>
+__global__ __launch_bounds__(kSampleThreads) void sample_sums_kernel(const SampleArgs a)
+{
+    sample_units<Integrand<F, D>, D, FP32, true>(a);
 }
 
 template <int F, int D, bool FP32>
@@ -29,6 +36,7 @@ const void* ptr_dew(int hint)
     case 1: return (const void*)&sample_kernel<F, D, FP32, kWaveHints[1]>;
     case 2: return (const void*)&sample_kernel<F, D, FP32, kWaveHints[2]>;
     case 3: return (const void*)&sample_kernel<F, D, FP32, kWaveHints[3]>;
+    case kSumsVariant: return (const void*)&sample_sums_kernel<F, D, FP32>;
     default: return (const void*)&sample_kernel<F, D, FP32, kWaveHints[0]>;
     }
 }

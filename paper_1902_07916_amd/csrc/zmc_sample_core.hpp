@@ -95,7 +95,10 @@ __device__ __forceinline__ void corner(const SlotDesc& sd, int level, uint64_t u
     }
 }
 
-template <class I, int D, bool FP32>
+// KEEP_S2: also accumulate the sum of squares (only the per-(cube, trial)
+// trace reads it; the estimator uses the sums alone).  Without it the
+// partial's second member is 0.
+template <class I, int D, bool FP32, bool KEEP_S2>
 __device__ __forceinline__ void sample_units(const SampleArgs& a)
 {
     constexpr int kWaves = kSampleThreads / 64;
@@ -168,7 +171,7 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
                     f = (q < nvalid) ? f : 0.0f;
                     const double fd = (double)f;
                     S1 += fd;
-                    S2 = fma(fd, fd, S2);
+                    if constexpr (KEEP_S2) S2 = fma(fd, fd, S2);
                 }
             }
         } else {
@@ -198,13 +201,13 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
                     double f = I::f64(p, x);
                     f = (q < nvalid) ? f : 0.0;
                     S1 += f;
-                    S2 = fma(f, f, S2);
+                    if constexpr (KEEP_S2) S2 = fma(f, f, S2);
                 }
             }
         }
 
         S1 = wave_sum(S1);
-        S2 = wave_sum(S2);
+        if constexpr (KEEP_S2) S2 = wave_sum(S2);
         // partial sums in unit order, [cube][trial * nch + chunk]: a wave's
         // consecutive units fill whole cache lines
         if (lane == 0) a.partial[sg.part_base + local] = make_double2(S1, S2);
