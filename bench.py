@@ -228,10 +228,10 @@ def run_serve(a) -> dict:
 
 # The paper's own timings on its hardware (Tables 1-4), seconds per run.
 PAPER_TIMES = {"f1_tf": (355.8, "1 x K40m"), "f1_numba": (313.5, "1 x K40m"), "f1_ray": (38.7, "1 x V100"),
-               "f2_numba": (69.7, "1 x K40m"), "f2_ray": (4.8, "1 x V100")}
+               "f2_numba": (69.7, "1 x K40m"), "f2_ray": (4.8, "1 x V100"), "f2_12d_ray": (47.6, "1 x V100")}
 # The paper's results for the same runs (Tables 1-4): value, standard deviation.
 PAPER_RESULTS = {"f1_tf": (-48.96, 0.76), "f1_numba": (-49.56, 1.40), "f1_ray": (-49.3971, 0.4845),
-                 "f2_numba": (1.00001, 0.00051), "f2_ray": (1.00035, 0.00064)}
+                 "f2_numba": (1.00001, 0.00051), "f2_ray": (1.00035, 0.00064), "f2_12d_ray": (1.00002, 0.00079)}
 
 
 def run_paper(a) -> dict:
