@@ -95,6 +95,53 @@ __device__ __forceinline__ void corner(const SlotDesc& sd, int level, uint64_t u
     }
 }
 
+// The 4 samples of a thread's group take words s*D + i, s = 0..3, i < D:
+// Philox blocks cb .. cb + D - 1 (4 words each).  Blocks are generated in
+// lockstep (independent chains for the issue pipeline).  For D >= kHalvesMinD
+// they are generated in two halves, the blocks holding samples 0-1 and then
+// the rest, and each half's samples are evaluated before the next half is
+// generated: the words live at once halve, which leaves registers for more
+// waves.  eval(q, w) gets sample q's D words in order.
+constexpr int kHalvesMinD = 10;
+
+template <int D, class Eval>
+__device__ __forceinline__ void group_samples(uint32_t cb, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                              uint32_t k1, Eval&& eval)
+{
+    constexpr int HA = D >= kHalvesMinD ? (D + 1) / 2 : D; // blocks of the first half
+    constexpr int HB = D - HA;
+    uint32_t ca[HA];
+    uint32_t wa[4 * HA];
+#pragma unroll
+    for (int k = 0; k < HA; ++k) ca[k] = cb + (uint32_t)k;
+    philox4x32_10_lockstep<HA>(ca, c1, c2, c3, k0, k1, wa);
+    constexpr int QA = HB > 0 ? 2 : 4; // samples wholly inside the first half
+#pragma unroll
+    for (int q = 0; q < QA; ++q) {
+        uint32_t ws[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) ws[i] = wa[q * D + i];
+        eval(q, ws);
+    }
+    if constexpr (HB > 0) {
+        uint32_t cbk[HB];
+        uint32_t wb[4 * HB];
+#pragma unroll
+        for (int k = 0; k < HB; ++k) cbk[k] = cb + (uint32_t)(HA + k);
+        philox4x32_10_lockstep<HB>(cbk, c1, c2, c3, k0, k1, wb);
+#pragma unroll
+        for (int q = 2; q < 4; ++q) {
+            uint32_t ws[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const int n = q * D + i; // words 2D .. 4HA - 1 are left from the first half
+                ws[i] = n < 4 * HA ? wa[n] : wb[n - 4 * HA];
+            }
+            eval(q, ws);
+        }
+    }
+}
+
 // KEEP_S2: also accumulate the sum of squares (only the per-(cube, trial)
 // trace reads it; the estimator uses the sums alone).  Without it the
 // partial's second member is 0.
@@ -156,23 +203,16 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
                 const int64_t s0 = 4 * g;
                 if (s0 >= N) break;
                 const int nvalid = (int)min((int64_t)4, N - s0); // < 4 only in a ragged last group
-                uint32_t w[4 * D];
-                uint32_t ctr[D];
-                const uint32_t cb = (uint32_t)g * (uint32_t)D;
-#pragma unroll
-                for (int k = 0; k < D; ++k) ctr[k] = cb + (uint32_t)k;
-                philox4x32_10_lockstep<D>(ctr, c1, c2, c3, k0, k1, w);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                group_samples<D>((uint32_t)g * (uint32_t)D, c1, c2, c3, k0, k1, [&](int q, const uint32_t* w) {
                     float v[D];
 #pragma unroll
-                    for (int i = 0; i < D; ++i) v[i] = unit_interval_f32(w[q * D + i]);
+                    for (int i = 0; i < D; ++i) v[i] = unit_interval_f32(w[i]);
                     float f = I::f32(p, v);
                     f = (q < nvalid) ? f : 0.0f;
                     const double fd = (double)f;
                     S1 += fd;
                     if constexpr (KEEP_S2) S2 = fma(fd, fd, S2);
-                }
+                });
             }
         } else {
             typename I::P64 p;
@@ -185,24 +225,17 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
                 const int64_t s0 = 4 * g;
                 if (s0 >= N) break;
                 const int nvalid = (int)min((int64_t)4, N - s0);
-                uint32_t w[4 * D];
-                uint32_t ctr[D];
-                const uint32_t cb = (uint32_t)g * (uint32_t)D;
-#pragma unroll
-                for (int k = 0; k < D; ++k) ctr[k] = cb + (uint32_t)k;
-                philox4x32_10_lockstep<D>(ctr, c1, c2, c3, k0, k1, w);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
+                group_samples<D>((uint32_t)g * (uint32_t)D, c1, c2, c3, k0, k1, [&](int q, const uint32_t* w) {
                     double x[D];
                     // x = fma(h, (2*(w>>9)+1) 2^-24, lo) computed as
                     // fma(h 2^-24, (w>>8)|1, lo): the same exact product
 #pragma unroll
-                    for (int i = 0; i < D; ++i) x[i] = fma(h24[i], (double)((w[q * D + i] >> 8) | 1u), lo[i]);
+                    for (int i = 0; i < D; ++i) x[i] = fma(h24[i], (double)((w[i] >> 8) | 1u), lo[i]);
                     double f = I::f64(p, x);
                     f = (q < nvalid) ? f : 0.0;
                     S1 += f;
                     if constexpr (KEEP_S2) S2 = fma(f, f, S2);
-                }
+                });
             }
         }
 
