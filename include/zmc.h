@@ -165,8 +165,10 @@ typedef struct {
     int32_t max_slots;      /* integrals resident at once (batch / serving);
                                0 = default 8192                               */
     int32_t queue_depth;    /* zmc_submit queue capacity; 0 = default 65536   */
-    void* serve_stream;     /* hipStream_t used by the serving thread; NULL =
-                               serving disabled                               */
+    void* serve_stream;     /* hipStream_t of the first serving lane; NULL =
+                               serving disabled.  With serving, 1/4 of the
+                               arena serves the synchronous calls and 3/4 is
+                               split evenly among the lanes                  */
     const char* tune_path;  /* JSON tile table written by the autotuner; NULL
                                or "" = built-in defaults                      */
     int32_t serve_lanes;    /* serving lanes (engine + thread + stream each;
@@ -200,7 +202,8 @@ typedef struct {
 } zmc_trace;
 
 /* Initialise the library on the current HIP device with the caller's arena.
- * EINVAL: NULL cfg/arena, arena_bytes < 64 MiB, misaligned arena.
+ * EINVAL: NULL cfg/arena, arena_bytes < 64 MiB, misaligned arena,
+ * serve_lanes outside 0..8, serve_chunk_samples < -1.
  * Calling it again after zmc_shutdown() is allowed. */
 int zmc_init(const zmc_config* cfg);
 
@@ -240,10 +243,14 @@ int zmc_integrate_request(const zmc_request* req, void* stream, zmc_result* out,
 int zmc_integrate_batch(const zmc_request* reqs, int n, void* stream, zmc_result* outs);
 
 /* Serving (continuous batching at level granularity): enqueue a copy of req
- * and return a ticket.  The serving thread admits queued requests whenever
- * slots and arena memory allow, runs every resident request's current level
- * in shared launches, and retires finished requests.  EINVAL: invalid
- * request; EBUSY: queue full; ENOINIT: no serve_stream was configured. */
+ * and return a ticket.  Each serving lane admits queued requests at its level
+ * boundaries whenever its slots and arena share allow (a busy lane whose next
+ * level is large leaves new requests to a lighter lane), runs every resident
+ * request's current level in shared launches, and retires finished requests.
+ * A request whose worst-case tree exceeds one lane's arena share ends with
+ * status ENOMEM.  Lanes run concurrently; calls may come from any thread.
+ * EINVAL: invalid request; EBUSY: queue full; ENOINIT: no serve_stream was
+ * configured. */
 int zmc_submit(const zmc_request* req, uint64_t* ticket);
 
 /* Result of a ticket.  wait = 0: returns EAGAIN while it runs; wait != 0:
