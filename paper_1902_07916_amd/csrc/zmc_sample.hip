@@ -18,7 +18,7 @@ template <int F, int D, bool FP32, int W>
 __global__ __launch_bounds__(kSampleThreads) __attribute__((amdgpu_waves_per_eu(W))) void sample_kernel(
     const SampleArgs a)
 {
-    sample_units<Integrand<F, D>, D, FP32, false>(a);
+    sample_units<Integrand<F, D>, D, FP32, false, W>(a);
 }
 
 // the variant that also keeps the sums of squares, for traced levels

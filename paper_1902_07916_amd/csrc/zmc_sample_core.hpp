@@ -142,10 +142,17 @@ __device__ __forceinline__ void group_samples(uint32_t cb, uint32_t c1, uint32_t
     }
 }
 
+template <bool B>
+struct BoolTag {
+    static constexpr bool value = B;
+};
+
 // KEEP_S2: also accumulate the sum of squares (only the per-(cube, trial)
 // trace reads it; the estimator uses the sums alone).  Without it the
 // partial's second member is 0.
-template <class I, int D, bool FP32, bool KEEP_S2>
+// W: the occupancy variant's minimum waves per SIMD (1 = unconstrained); it
+// decides whether whole and ragged groups get loops of their own (below).
+template <class I, int D, bool FP32, bool KEEP_S2, int W = 1>
 __device__ __forceinline__ void sample_units(const SampleArgs& a)
 {
     constexpr int kWaves = kSampleThreads / 64;
@@ -195,24 +202,42 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
         const int64_t g0 = (int64_t)chunk * G * 64 + lane;
 
         double S1 = 0.0, S2 = 0.0;
+        // Groups of 4 points; with N a multiple of 4 every group a lane
+        // reaches is whole, otherwise the group holding point N - 1 is cut
+        // short and its points past N count as 0.  Where registers allow,
+        // the two cases are separate loops, so that whole groups carry no
+        // per-point mask (1-3% faster).  The second loop costs registers: in
+        // the 7- and 8-wave variants from D = 7 (8-wave: from D = 5) it made
+        // the allocator spill (up to 66% slower), and from D = kHalvesMinD
+        // on the mask costs under 1%; those keep the one masked loop.
+        constexpr bool kWholeLoop = D < kHalvesMinD && (W <= 5 || (W == 7 && D <= 6));
         if constexpr (FP32) {
             typename I::P32 p;
             I::prep32(sd, lo, h, p);
-            for (int j = 0; j < G; ++j) {
-                const int64_t g = g0 + (int64_t)j * 64;
-                const int64_t s0 = 4 * g;
-                if (s0 >= N) break;
-                const int nvalid = (int)min((int64_t)4, N - s0); // < 4 only in a ragged last group
-                group_samples<D>((uint32_t)g * (uint32_t)D, c1, c2, c3, k0, k1, [&](int q, const uint32_t* w) {
-                    float v[D];
+            auto run = [&](auto ragged) {
+                for (int j = 0; j < G; ++j) {
+                    const int64_t g = g0 + (int64_t)j * 64;
+                    const int64_t s0 = 4 * g;
+                    if (s0 >= N) break;
+                    int nvalid = 4;
+                    if constexpr (decltype(ragged)::value) nvalid = (int)min((int64_t)4, N - s0);
+                    group_samples<D>((uint32_t)g * (uint32_t)D, c1, c2, c3, k0, k1, [&](int q, const uint32_t* w) {
+                        float v[D];
 #pragma unroll
-                    for (int i = 0; i < D; ++i) v[i] = unit_interval_f32(w[i]);
-                    float f = I::f32(p, v);
-                    f = (q < nvalid) ? f : 0.0f;
-                    const double fd = (double)f;
-                    S1 += fd;
-                    if constexpr (KEEP_S2) S2 = fma(fd, fd, S2);
-                });
+                        for (int i = 0; i < D; ++i) v[i] = unit_interval_f32(w[i]);
+                        float f = I::f32(p, v);
+                        if constexpr (decltype(ragged)::value) f = (q < nvalid) ? f : 0.0f;
+                        const double fd = (double)f;
+                        S1 += fd;
+                        if constexpr (KEEP_S2) S2 = fma(fd, fd, S2);
+                    });
+                }
+            };
+            if constexpr (kWholeLoop) {
+                if ((N & 3) == 0) run(BoolTag<false>{});
+                else run(BoolTag<true>{});
+            } else {
+                run(BoolTag<true>{});
             }
         } else {
             typename I::P64 p;
@@ -220,22 +245,31 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
             double h24[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) h24[i] = ldexp(h[i], -24);
-            for (int j = 0; j < G; ++j) {
-                const int64_t g = g0 + (int64_t)j * 64;
-                const int64_t s0 = 4 * g;
-                if (s0 >= N) break;
-                const int nvalid = (int)min((int64_t)4, N - s0);
-                group_samples<D>((uint32_t)g * (uint32_t)D, c1, c2, c3, k0, k1, [&](int q, const uint32_t* w) {
-                    double x[D];
-                    // x = fma(h, (2*(w>>9)+1) 2^-24, lo) computed as
-                    // fma(h 2^-24, (w>>8)|1, lo): the same exact product
+            auto run = [&](auto ragged) {
+                for (int j = 0; j < G; ++j) {
+                    const int64_t g = g0 + (int64_t)j * 64;
+                    const int64_t s0 = 4 * g;
+                    if (s0 >= N) break;
+                    int nvalid = 4;
+                    if constexpr (decltype(ragged)::value) nvalid = (int)min((int64_t)4, N - s0);
+                    group_samples<D>((uint32_t)g * (uint32_t)D, c1, c2, c3, k0, k1, [&](int q, const uint32_t* w) {
+                        double x[D];
+                        // x = fma(h, (2*(w>>9)+1) 2^-24, lo) computed as
+                        // fma(h 2^-24, (w>>8)|1, lo): the same exact product
 #pragma unroll
-                    for (int i = 0; i < D; ++i) x[i] = fma(h24[i], (double)((w[i] >> 8) | 1u), lo[i]);
-                    double f = I::f64(p, x);
-                    f = (q < nvalid) ? f : 0.0;
-                    S1 += f;
-                    if constexpr (KEEP_S2) S2 = fma(f, f, S2);
-                });
+                        for (int i = 0; i < D; ++i) x[i] = fma(h24[i], (double)((w[i] >> 8) | 1u), lo[i]);
+                        double f = I::f64(p, x);
+                        if constexpr (decltype(ragged)::value) f = (q < nvalid) ? f : 0.0;
+                        S1 += f;
+                        if constexpr (KEEP_S2) S2 = fma(f, f, S2);
+                    });
+                }
+            };
+            if constexpr (kWholeLoop) {
+                if ((N & 3) == 0) run(BoolTag<false>{});
+                else run(BoolTag<true>{});
+            } else {
+                run(BoolTag<true>{});
             }
         }
 
