@@ -52,10 +52,11 @@ def valu_instructions_per_sample(integrand: str, D: int, eval_: str) -> dict:
     if eval_ == "fp32":
         ints, fp32, fp64, trans = rng + D, float(D), 2.0, 0.0
         if integrand in ("sin_sum", "genz_osc"):
-            # low part of the cube phase; r - rint(r), fold to [-1/4, 1/4]
-            # (compare, copysign, select), t^2, 6 FMA, *t
-            fp32 += 10
-            ints += 3
+            # high part of the cube phase; r - rint(r) (rint, sub), fold
+            # a = min(|t|, 1/2 - |t|) (sub, min), a^2, 6 FMA, *a; the sign
+            # back on (copysign, an integer bit-field insert)
+            fp32 += 11
+            ints += 1
         elif integrand in ("gauss", "genz_gauss"):
             fp32 += D + 2          # t^2 sum, scale, A *
             trans += 1             # exp2

@@ -23,17 +23,20 @@ constexpr double kInvTwoPi = 0.15915494309189533576888376337251;
 constexpr double kLog2e = 1.4426950408889634073599246810019;
 constexpr double kOneMinus = 1.0 - 0x1p-24;
 
-// sin(2 pi r): r is reduced to t in [-1/4, 1/4] by the exact steps
-// t = r - rint(r) and t = (+-1/2) - t, which keep the result odd-symmetric
-// (so its error has no mean over a period), then the Taylor series of
-// sin(2 pi t) through t^13 (truncation < 7e-10) is summed by Horner in t^2.
-// Coefficients: (-1)^k (2 pi)^(2k+1) / (2k+1)!.
+// sin(2 pi r): r is reduced by the exact steps t = r - rint(r) and
+// a = min(|t|, 1/2 - |t|) in [0, 1/4], which keep the result odd-symmetric
+// (so its error has no mean over a period); the Taylor series of
+// sin(2 pi a) through a^13 (truncation < 7e-10) is summed by Horner in a^2
+// and takes the sign of t.  Coefficients: (-1)^k (2 pi)^(2k+1) / (2k+1)!.
 __device__ __forceinline__ float sin_rev(float r)
 {
-    float t = r - __builtin_rintf(r);
-    const float half = __builtin_copysignf(0.5f, t);
-    t = (__builtin_fabsf(t) > 0.25f) ? half - t : t;
-    const float t2 = t * t;
+    const float t = r - __builtin_rintf(r);
+    // fold |t| in [0, 1/2] to a in [0, 1/4] with sin(2 pi |t|) = sin(2 pi a):
+    // 1/2 - |t| is exact for |t| >= 1/4, and min() is a floating-point
+    // instruction, so the fold needs no integer select
+    const float at = __builtin_fabsf(t);
+    const float a = __builtin_fminf(at, 0.5f - at);
+    const float t2 = a * a;
     float p = 3.8199524879455566f;
     p = __builtin_fmaf(p, t2, -15.094642639160156f);
     p = __builtin_fmaf(p, t2, 42.058692932128906f);
@@ -41,7 +44,7 @@ __device__ __forceinline__ float sin_rev(float r)
     p = __builtin_fmaf(p, t2, 81.6052474975586f);
     p = __builtin_fmaf(p, t2, -41.34170150756836f);
     p = __builtin_fmaf(p, t2, 6.2831854820251465f);
-    return p * t;
+    return __builtin_copysignf(p * a, t); // the polynomial is odd: sin(2 pi t) = sign(t) sin(2 pi a)
 }
 
 // frac(x) in FP64 for the per-cube phase offsets.
