@@ -103,9 +103,11 @@ def test_serving_mix_matches_alone(zi, orc):
 
 def test_serving_cancel_and_errors(zi):
     from paper_1902_07916_amd import ZmcError, make_request
-    # ~2e10 points per level: still running when the cancel arrives, unless
-    # the submitting thread is descheduled for that long
-    big = make_request("genz_osc", [0.1] + [2.0] * 8, [0.0] * 8, [1.0] * 8, 3, 1 << 20, 3, 4, 5.0, 1, eval="fp32")
+    # ~2e10 points at the root level: still running when the cancel arrives,
+    # unless the submitting thread is descheduled for that long.  One
+    # refinement keeps its worst-case tree inside one serving lane's share of
+    # the arena (a deeper tree would be refused with ENOMEM at admission).
+    big = make_request("genz_osc", [0.1] + [2.0] * 8, [0.0] * 8, [1.0] * 8, 3, 1 << 20, 3, 1, 5.0, 1, eval="fp32")
     t = zi.submit(big)
     zi.cancel(t)
     r = zi.poll(t, wait=True)
