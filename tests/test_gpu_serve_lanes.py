@@ -61,6 +61,21 @@ def test_chunked_lanes_match_sync(zl):
     assert launches > 10  # the levels really were cut into many launches
 
 
+def test_chunked_ragged_point_counts_match_sync(zl):
+    # N not a multiple of 4 takes the masked loop; cut into many launches it
+    # must still give bitwise the synchronous result, alone and beside
+    # requests of the same bucket with whole groups
+    from paper_1902_07916_amd import workloads as W
+    base = W.serving_stream(rate=400.0, duration=0.05, samples=1536, max_root_cubes=1024)
+    ws = [dict(w, samples=n) for (_, w), n in zip(base[:6], (1537, 1536, 3001, 1538, 4096, 1539))]
+    reqs = [request(w) for w in ws]
+    tickets = [zl.submit(rq) for rq in reqs]
+    served = [zl.poll(t, wait=True) for t in tickets]
+    for rq, s in zip(reqs, served):
+        assert s.status == 0
+        assert _same(s, zl.integrate_request(rq))
+
+
 def test_chunked_user_integrand_matches_sync(zl):
     import paper_1902_07916_amd as zmc
     from paper_1902_07916_amd import workloads as W
