@@ -169,6 +169,10 @@ __device__ bool last_tile_of_segment(int32_t* count, int si, int64_t n_tiles)
 {
     __shared__ int last;
     __syncthreads();
+    // a one-tile segment has no other block to wait for: its own record is
+    // visible to the block after the barrier, and no device-scope fence (an
+    // L2 write-back on this chip) is needed
+    if (n_tiles == 1) return true;
     if (threadIdx.x == 0) {
         __threadfence(); // release this block's tile record
         const int old = atomicAdd(&count[si], 1);
