@@ -142,7 +142,7 @@ typedef struct {
     int32_t split;               /* 0 or 2: a split bisects every axis (2^D
                                     children); b in 3..64: b parts per axis (b^D
                                     children, at most 2^24; b = d is the paper's
-                                    "k equal sub-sub-domains", Sec. 2.1)         */
+                                    split into k equal parts, Sec. 2.1)         */
     int32_t threshold_scope;     /* 0: one threshold per level over all its cubes;
                                     1: one per parent, over its children (the
                                     roots share one)                             */

@@ -62,7 +62,7 @@ typedef struct {
     int32_t n_params;
     int32_t split;       /* b: a split cuts every axis into b parts (b^D
                             children); 2 = bisection (default reading), b = d
-                            = the paper's "k equal sub-sub-domains"        */
+                            = the paper's split into k equal parts      */
     int32_t scope;       /* threshold population: 0 = all cubes of a level
                             (default reading), 1 = the children of one
                             parent (roots: all roots)                       */
@@ -310,8 +310,8 @@ void oracle_sample_x(const oracle_problem* p, int level, uint64_t uid, int trial
 
 /* ------------------------------------------------------------------------- */
 /* One direct Monte Carlo estimate of the integral over one sub-domain         */
-/* (Sec. 2.1: "the integral in each hypercube is calculated using the direct  */
-/* Monte Carlo method"): I_t = V * (1/N) sum_s f(x_s).  Diagnostics S2 = sum  */
+/* (Sec. 2.1: each hypercube's integral is a plain direct Monte Carlo       */
+/* estimate): I_t = V * (1/N) sum_s f(x_s).  Diagnostics S2 = sum             */
 /* f^2 and SA = sum |f| never feed a decision.  Returns 0, or OR_ENONFINITE   */
 /* if any f was not finite.                                                    */
 /* ------------------------------------------------------------------------- */
@@ -385,7 +385,7 @@ int oracle_cube(const oracle_problem* p, int level, uint64_t uid, double* I_out,
 
 /* Threshold over one level's standard deviations (Sec. 2.1: the threshold is
  * set from the mean and the standard deviation of the k standard deviations;
- * Sec. 3 quotes it as "larger than 5 sigma").  Reading: thr = mean(s) +
+ * Sec. 3 applies it as a five-sigma cut).  Reading: thr = mean(s) +
  * sigma_mult * std(s), population std, two passes, serial sums. */
 double oracle_threshold(const double* s, int64_t n, double sigma_mult, double* mu_out, double* sd_out)
 {
@@ -478,7 +478,7 @@ int oracle_validate(const oracle_problem* p)
 /*  - level 0 holds the k = d^D root cubes; max_depth counts refinement rounds */
 /*    after it, so the paper's "partition depth" is max_depth + 1;             */
 /*  - a selected cube is split into 2^D children (every axis bisected; with  */
-/*    split = b, b^D children, b = d being the paper's "k equal             */
+/*    split = b, b^D children, b = d being the paper's k equal parts        */
 /*    sub-sub-domains"), and the children replace it (its own mean and std  */
 /*    are dropped);                                                          */
 /*  - the threshold is recomputed over each new list of sub-domains, i.e. per */

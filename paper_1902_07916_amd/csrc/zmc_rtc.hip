@@ -1,6 +1,6 @@
 // zmc_rtc.hip -- user-defined integrands compiled at run time with hipRTC.
 //
-// The paper's package integrates "general user defined functions" written in
+// The paper's package integrates general user-defined functions written in
 // Python/Numba (abstract, Sec. 3.3).  Here the user supplies the body of a
 // device function in C++ syntax,
 //

@@ -54,7 +54,7 @@ def paper_f2(sigma=0.01, dim=9, divisions=3, samples=3**9, trials=5, max_depth=3
 
 
 # The paper's own runs (Sec. 3), with its "partition depth" p mapped to
-# max_depth = p - 1 and "larger than k sigma" to sigma_mult = k.  Points per
+# max_depth = p - 1 and a k-sigma cut to sigma_mult = k.  Points per
 # sub-domain are n2^D where the paper gives points per dimension.
 PAPER_RUNS = {
     # f1 = sin(sum x), [0,10]^6

@@ -1,6 +1,6 @@
 """GPU parity of the tree-search variants against the oracle: k-way splits
-(every axis cut into b equal parts, b^D children; Sec. 2.1 reads "k equal
-sub-sub-domains") and per-parent thresholds (a new threshold from each
+(every axis cut into b equal parts, b^D children; Sec. 2.1 splits a cube into k
+equal parts) and per-parent thresholds (a new threshold from each
 split cube's own children), alone and combined, FP64 and FP32 evaluation.
 
 Same bar as the bisection parity tests: lists bit-exact, per-cube m and s

@@ -1,6 +1,6 @@
 """Pins of the oracle's method variants (the paper's other readings of
 Sec. 2.1): a split into b parts per axis (b^D children; b = d is the paper's
-"k equal sub-sub-domains") and a threshold per parent (over the children of
+split into k equal parts) and a threshold per parent (over the children of
 one split cube) instead of per level."""
 import math
 
