@@ -242,6 +242,15 @@ int zmc_integrate_request(const zmc_request* req, void* stream, zmc_result* out,
  * arena together, those still resident at that level get ENOMEM. */
 int zmc_integrate_batch(const zmc_request* reqs, int n, void* stream, zmc_result* outs);
 
+/* Worst-case device bytes of req's tree: the largest level's list, work
+ * arrays and next list, with every level's selections bounded by Cantelli's
+ * inequality (at most n / (1 + sigma_mult^2) of n cubes exceed mean +
+ * sigma_mult * std; n - 1 when sigma_mult = 0) and by max_cubes_per_level.
+ * It is the reservation serving admission makes and the size a batch member
+ * may not exceed alone.  Needs no zmc_init() (uses the built-in tile table
+ * before it).  EINVAL as for zmc_integrate_request(). */
+int zmc_request_bytes(const zmc_request* req, uint64_t* bytes);
+
 /* Serving (continuous batching at level granularity): enqueue a copy of req
  * and return a ticket.  Each serving lane admits queued requests at its level
  * boundaries whenever its slots and arena share allow (a busy lane whose next

@@ -437,6 +437,15 @@ int zmc_integrate_request(const zmc_request* req, void* stream, zmc_result* out,
     return rc;
 }
 
+int zmc_request_bytes(const zmc_request* req, uint64_t* bytes)
+{
+    if (!req || !bytes) return fail(ZMC_EINVAL, "NULL request or output");
+    const int rc = validate(*req);
+    if (rc != ZMC_OK) return rc;
+    *bytes = (uint64_t)request_bytes(*req, g.tiles);
+    return ZMC_OK;
+}
+
 int zmc_integrate(int integrand_id, const double* params, int n_params, int dim, const double* lower,
                   const double* upper, int divisions_per_axis, int64_t samples_per_cube, int trials, int max_depth,
                   double sigma_mult, uint64_t seed, int eval, void* stream, zmc_result* out)
@@ -582,7 +591,7 @@ const char* zmc_strerror(int status)
     switch (status) {
     case ZMC_OK: return "ok";
     case ZMC_EINVAL: return last_error()[0] ? last_error() : "invalid argument";
-    case ZMC_ENOMEM: return "arena exhausted";
+    case ZMC_ENOMEM: return last_error()[0] ? last_error() : "arena exhausted";
     case ZMC_ENONFINITE: return "integrand produced a non-finite value";
     case ZMC_EDEVICE: return last_error()[0] ? last_error() : "HIP error";
     case ZMC_EAGAIN: return "not finished";

@@ -188,17 +188,21 @@ void Engine::teardown()
 // Chunk of one sampling unit (one wave): 4 * 64 * groups points, with groups
 // the smaller of the tile table's cap for the bucket and what N needs, so a
 // request's chunking depends only on its own parameters.
-int Engine::groups_of(const zmc_request& r) const
+int groups_for(const zmc_request& r, const TileTable& t)
 {
     const int64_t need = ceil_div(r.samples_per_cube, 4LL * 64);
-    return (int)std::max<int64_t>(1, std::min<int64_t>(need, tiles_->get(r.integrand, r.dim, r.eval)));
+    return (int)std::max<int64_t>(1, std::min<int64_t>(need, t.get(r.integrand, r.dim, r.eval)));
 }
 
-int Engine::nch_of(const zmc_request& r) const
+int chunks_for(const zmc_request& r, const TileTable& t)
 {
-    const int64_t chunk = 4LL * 64 * groups_of(r);
+    const int64_t chunk = 4LL * 64 * groups_for(r, t);
     return (int)ceil_div(r.samples_per_cube, chunk);
 }
+
+int Engine::groups_of(const zmc_request& r) const { return groups_for(r, *tiles_); }
+
+int Engine::nch_of(const zmc_request& r) const { return chunks_for(r, *tiles_); }
 
 int Engine::capacity(int integrand, int dim, int eval, bool keep_s2)
 {
@@ -246,9 +250,16 @@ int Engine::fill_slot_desc(int slot, const zmc_request& r, hipStream_t st)
 
 // Bytes one integral can hold at its largest level: current list + work
 // arrays + next list, with the next level bounded by Cantelli's inequality
-// (at most n / (1 + sigma_mult^2) cubes exceed mean + sigma_mult * std) and
-// by the per-level cap.
-size_t Engine::reservation_bytes(const zmc_request& r) const
+// (at most n / (1 + sigma_mult^2) cubes exceed mean + sigma_mult * std; with
+// per-parent thresholds the bound holds in every sibling group, so for the
+// level too) and by the per-level cap.  Per cube of a level, step() takes
+// its uid, the partial sums, m, s, the selection byte, a share of the tile
+// records (96 bytes per 1024 cubes) and, with per-parent thresholds, a share
+// of the per-group thresholds (8 bytes per kids cubes); every allocation is
+// rounded up to 256 bytes.
+size_t Engine::reservation_bytes(const zmc_request& r) const { return request_bytes(r, *tiles_); }
+
+size_t request_bytes(const zmc_request& r, const TileTable& t)
 {
     const int64_t cap = r.max_cubes_per_level > 0 ? r.max_cubes_per_level : ZMC_DEFAULT_MAX_CUBES;
     const int64_t k = (int64_t)ipow_u64((uint64_t)r.divisions_per_axis, r.dim);
@@ -264,8 +275,12 @@ size_t Engine::reservation_bytes(const zmc_request& r) const
         n = nn;
         if (n == 0) break;
     }
-    const int64_t per_cube = 8 + 16LL * r.trials * nch_of(r) + 8 + 8 + 1 + 1;
-    return (size_t)(worst * per_cube + worst_next * 8 + 4 * 4096);
+    const int64_t kids = kids_of(r);
+    const int64_t per_group_thr = r.threshold_scope == 1 ? (8 + kids - 1) / kids : 0;
+    const int64_t per_tile = (int64_t)sizeof(TileRec);
+    const int64_t per_cube = 8 + 16LL * r.trials * chunks_for(r, t) + 8 + 8 + 1 + per_group_thr;
+    const int64_t tiles = ceil_div(worst, kTileCubes) + 1;
+    return (size_t)(worst * per_cube + tiles * per_tile + worst_next * 8 + 8 * 256 + 4 * 4096);
 }
 
 void Engine::record_level(HostSlot& hs, const SegStats& S, int64_t n, double ms, float sample_ms, int launches)

@@ -108,6 +108,13 @@ struct LiveSeg {
 
 constexpr int64_t ZMC_DEFAULT_MAX_CUBES = 1LL << 24;
 
+// 4-point groups per lane in one sampling unit, and units (chunks) per
+// (cube, trial), of a request under a tile table.
+int groups_for(const zmc_request& r, const TileTable& t);
+int chunks_for(const zmc_request& r, const TileTable& t);
+// Worst-case device bytes of one request's tree (see Engine::reservation_bytes).
+size_t request_bytes(const zmc_request& r, const TileTable& t);
+
 class Engine {
 public:
     int setup(char* base, size_t bytes, int max_slots, const TileTable* tiles, int device);

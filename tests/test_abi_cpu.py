@@ -145,3 +145,55 @@ def test_split_limits_agree_with_oracle(lib, orc):
                     ok = orc.validate(p) == 0 and d ** D <= (1 << 24)
                     assert (rc == _abi.ENOINIT) == ok, (D, b, d, dep, rc)
                     assert rc in (_abi.ENOINIT, _abi.EINVAL)
+
+
+def _step_bytes(n, n_next, trials, nch, kids, scope, level):
+    """Device bytes the level driver holds while stepping a level of n cubes
+    whose next level has n_next cubes: the current uid list, the partial sums
+    (one 16-byte pair per (cube, trial, chunk)), m, s, the selection bytes,
+    the 96-byte tile records (one per 1024 cubes), the per-parent thresholds
+    (one per sibling group) and the next uid list, each rounded to 256 bytes."""
+    r = lambda b: (b + 255) // 256 * 256  # noqa: E731
+    groups = n // kids if (scope == 1 and level > 0 and n > kids) else 0
+    return (r(8 * n) + r(16 * trials * nch * n) + 2 * r(8 * n) + r(n) + r(96 * -(-n // 1024)) + r(8 * groups)
+            + r(8 * n_next))
+
+
+def test_request_bytes_bounds_every_level(lib):
+    """The admission reservation covers every level of the worst-case tree
+    (Cantelli's bound on the selections, the level cap), for both threshold
+    scopes and small D, where the per-parent thresholds weigh most."""
+    import math
+
+    from paper_1902_07916_amd import _abi, make_request
+    checked = 0
+    for D in (1, 2, 3):
+        for scope in (0, 1):
+            for split in (0, 3):
+                for sigma in (0.0, 0.5, 1.0, 5.0):
+                    big = {1: 200000, 2: 447, 3: 58}[D]  # ~2e5 roots: the per-cube terms dominate
+                    for d, N, n1, depth in ((5, 1000, 2, 4), (big, 4096, 3, 3), (big, 128, 5, 2)):
+                        prm = [0.2, 1.0] + [0.0] * D
+                        q = make_request("gauss", prm, [0.0] * D, [1.0] * D, d, N, n1, depth, sigma, 1,
+                                         split=split, threshold_scope=scope)
+                        got = C.c_uint64()
+                        assert lib.zmc_request_bytes(C.byref(q), C.byref(got)) == 0
+                        kids = (split or 2) ** D
+                        groups = min(-(-N // 256), 32)
+                        nch = -(-N // (256 * groups))
+                        n = d ** D
+                        sizes = [n]
+                        for _ in range(depth):
+                            nsel = n - 1 if sigma == 0 else math.floor(n / (1 + sigma * sigma))
+                            nn = nsel * kids
+                            if nn > (1 << 24) or nn == 0:
+                                break
+                            sizes.append(nn)
+                            n = nn
+                        need = max(_step_bytes(a, b, n1, nch, kids, scope, l)
+                                   for l, (a, b) in enumerate(zip(sizes, sizes[1:] + [0])))
+                        assert got.value >= need, (D, scope, split, sigma, d, got.value, need)
+                        checked += 1
+    assert checked == 144
+    bad = make_request("gauss", [0.2], [0.0], [1.0], 2, 16, 3, 1, 1.0, 1)
+    assert lib.zmc_request_bytes(C.byref(bad), C.byref(C.c_uint64())) == _abi.EINVAL
