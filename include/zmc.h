@@ -230,6 +230,24 @@ int zmc_integrate(int integrand_id, const double* params, int n_params, int dim,
  * optional trace (NULL = none). */
 int zmc_integrate_request(const zmc_request* req, void* stream, zmc_result* out, zmc_trace* trace);
 
+/* zmc_integrate_request() without a trace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation): the call allocates nothing.  Its level arrays live
+ * in a static device array of the library (64 MiB per device, held from the
+ * first zmc_init() on that device until the process ends) instead of the
+ * arena; its pinned staging was allocated by zmc_init().  Results are bitwise
+ * those of zmc_integrate_request() (the same kernels).  Calls share that one
+ * array and keep no state in it between calls (the level counters it holds
+ * are left at zero by every launch); the library serialises them, and each
+ * call synchronises its stream before returning, so calls do not overlap on
+ * the device: a caller that replays such a call asynchronously (e.g. from a
+ * captured graph) must not let two of them run at once.
+ * ENOMEM (before any device work, with the sizes in zmc_strerror) when the
+ * request's worst-case tree (zmc_request_bytes) exceeds the static array;
+ * EINVAL for a run-time compiled integrand (loading its code allocates) and
+ * as for zmc_integrate_request(); ENOINIT before zmc_init(). */
+int zmc_integrate_noalloc(const zmc_request* req, void* stream, zmc_result* out);
+
 /* Integrate n independent requests together (each with its own threshold per
  * level): all their cubes are evaluated by the same launches, level by level.
  * outs[i] receives request i's result; each result is bitwise the one

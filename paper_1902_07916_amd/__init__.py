@@ -221,6 +221,22 @@ class Integrator:
             tdict = self._collect_trace(tr, bufs, req, out.levels_run)
         return Result.from_c(out, tdict)
 
+    def integrate_noalloc(self, req: _abi.Request, raise_on_error: bool = True) -> Result:
+        """zmc_integrate_noalloc: the request on the library's static device
+        scratch (64 MiB), allocating nothing during the call."""
+        self._live()
+        out = _abi.Result()
+        rc = self._lib.zmc_integrate_noalloc(C.byref(req), self._stream(), C.byref(out))
+        if rc != 0 and raise_on_error:
+            raise ZmcError(rc, "zmc_integrate_noalloc")
+        return Result.from_c(out)
+
+    def request_bytes(self, req: _abi.Request) -> int:
+        """zmc_request_bytes: worst-case device bytes of the request's tree."""
+        out = C.c_uint64()
+        check(self._lib.zmc_request_bytes(C.byref(req), C.byref(out)), "zmc_request_bytes")
+        return out.value
+
     def integrate_batch(self, reqs) -> list:
         self._live()
         arr = (_abi.Request * len(reqs))(*reqs)

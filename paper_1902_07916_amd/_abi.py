@@ -29,7 +29,7 @@ F_TRUNCATED, F_RTOL_MET = 1, 2
 EXPORTS = ("zmc_init", "zmc_shutdown", "zmc_integrate", "zmc_integrate_request", "zmc_integrate_batch",
            "zmc_submit", "zmc_poll", "zmc_cancel", "zmc_serve_stats", "zmc_debug_philox", "zmc_debug_points",
            "zmc_cube_estimates", "zmc_strerror", "zmc_version", "zmc_struct_size", "zmc_register_integrand",
-           "zmc_request_bytes")
+           "zmc_request_bytes", "zmc_integrate_noalloc")
 
 
 class Result(C.Structure):
@@ -108,6 +108,7 @@ def load(path: str = LIB_PATH):
     L.zmc_struct_size.argtypes = [i32]
     L.zmc_register_integrand.argtypes = [C.c_char_p, i32, C.POINTER(C.c_int)]
     L.zmc_request_bytes.argtypes = [Q, C.POINTER(u64)]
+    L.zmc_integrate_noalloc.argtypes = [Q, vp, R]
     for i, T in enumerate((Result, Request, Config, Trace)):
         if L.zmc_struct_size(i) != C.sizeof(T):
             raise RuntimeError("ABI mismatch for %s: C %d vs ctypes %d" % (T.__name__, L.zmc_struct_size(i),

@@ -4,6 +4,7 @@
 // tree-level granularity).
 #include <hip/hip_runtime.h>
 #include <math.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <atomic>
@@ -74,10 +75,25 @@ struct Context {
     Engine sync_eng;
     std::mutex sync_mu;
     Server* server = nullptr;
+    // zmc_integrate_noalloc: a one-integral engine over the device scratch
+    Engine static_eng;
+    std::mutex static_mu;
 };
 
 Context g;
 std::mutex g_init_mu;
+
+// Device scratch of zmc_integrate_noalloc, for callers that cannot allocate
+// device memory: the arena of a one-integral engine, held by every device
+// the library runs on until the process ends.  In host code `scratch` is a
+// host-side stand-in for the symbol, not a device address; its address on a
+// device comes from hipGetSymbolAddress (once per device, in zmc_init, with
+// that device current) and only that address is ever passed on.
+constexpr size_t kStaticScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+
 
 uint64_t ipow_sat(uint64_t b, int e, bool* ovf)
 {
@@ -356,6 +372,7 @@ int zmc_init(const zmc_config* cfg)
     if (g.inited) {
         stop_server();
         g.sync_eng.teardown();
+        g.static_eng.teardown();
         g.inited = false;
     }
     if (hipGetDevice(&g.device) != hipSuccess) return fail(ZMC_EDEVICE, "hipGetDevice failed");
@@ -370,6 +387,25 @@ int zmc_init(const zmc_config* cfg)
     if (cfg->serve_stream) sync_bytes = (bytes / 4) & ~(size_t)255;
     int rc = g.sync_eng.setup(base, sync_bytes, slots, &g.tiles, g.device);
     if (rc != ZMC_OK) return rc;
+    if (g.device < 0 || g.device >= kMaxDevices) {
+        g.sync_eng.teardown();
+        return fail(ZMC_EDEVICE, "zmc_init: device id out of range");
+    }
+    if (!g_scratch_ptr[g.device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            g.sync_eng.teardown();
+            return fail(ZMC_EDEVICE, (std::string("zmc_init: hipGetSymbolAddress(scratch): ") +
+                                      hipGetErrorString(e)).c_str());
+        }
+        g_scratch_ptr[g.device] = p;
+    }
+    rc = g.static_eng.setup((char*)g_scratch_ptr[g.device], kStaticScratchBytes, 1, &g.tiles, g.device);
+    if (rc != ZMC_OK) {
+        g.sync_eng.teardown();
+        return rc;
+    }
     if (cfg->serve_stream) {
         const int n_lanes = cfg->serve_lanes > 0 ? cfg->serve_lanes : 2;
         Server* S = new Server();
@@ -398,6 +434,7 @@ int zmc_init(const zmc_config* cfg)
             }
             delete S;
             g.sync_eng.teardown();
+            g.static_eng.teardown();
             return rc;
         }
         g.server = S;
@@ -416,6 +453,10 @@ int zmc_shutdown(void)
     {
         std::lock_guard<std::mutex> lk2(g.sync_mu);
         g.sync_eng.teardown();
+    }
+    {
+        std::lock_guard<std::mutex> lk3(g.static_mu);
+        g.static_eng.teardown();
     }
     g.inited = false;
     return ZMC_OK;
@@ -444,6 +485,37 @@ int zmc_request_bytes(const zmc_request* req, uint64_t* bytes)
     if (rc != ZMC_OK) return rc;
     *bytes = (uint64_t)request_bytes(*req, g.tiles);
     return ZMC_OK;
+}
+
+int zmc_integrate_noalloc(const zmc_request* req, void* stream, zmc_result* out)
+{
+    if (!req || !out) return fail(ZMC_EINVAL, "NULL request or result");
+    init_result(*out);
+    int rc = validate(*req);
+    if (rc != ZMC_OK) {
+        out->status = rc;
+        return rc;
+    }
+    if (req->integrand >= kUserBase) {
+        out->status = ZMC_EINVAL;
+        return fail(ZMC_EINVAL, "zmc_integrate_noalloc: run-time compiled integrands load code objects (an "
+                                "allocation); use zmc_integrate_request");
+    }
+    if (!g.inited) return fail(ZMC_ENOINIT, "zmc_init has not been called");
+    std::lock_guard<std::mutex> lk(g.static_mu);
+    const size_t need = g.static_eng.reservation_bytes(*req);
+    if (need > g.static_eng.budget_bytes()) {
+        out->status = ZMC_ENOMEM;
+        char msg[192];
+        snprintf(msg, sizeof msg,
+                 "zmc_integrate_noalloc: the request's worst-case tree needs %zu bytes; the static scratch "
+                 "holds %zu",
+                 need, g.static_eng.budget_bytes());
+        return fail(ZMC_ENOMEM, msg);
+    }
+    rc = g.static_eng.run(req, 1, (hipStream_t)stream, out, nullptr);
+    if (rc == ZMC_OK && out->status != ZMC_OK) rc = out->status;
+    return rc;
 }
 
 int zmc_integrate(int integrand_id, const double* params, int n_params, int dim, const double* lower,
