@@ -97,13 +97,25 @@ typedef enum {
  *  ZMC_EVAL_FP64: x and f in FP64; x is bitwise the value of step 2 above.
  *  ZMC_EVAL_FP32: x and f in FP32 using cube-relative coordinates (offsets
  *                 and phases formed in FP64 per cube) and the hardware
- *                 transcendental units. */
+ *                 transcendental units; the FP32 value is f divided by a
+ *                 per-cube FP64 scale (the amplitude and, for the Gaussian
+ *                 families, the value at the cube's point nearest the peak;
+ *                 the product of c_i^2 for the product peak; the value at the
+ *                 lower corner for the corner peak; the largest |x_i|^p_i for
+ *                 the monomial), applied to each FP64 sum. */
 typedef enum { ZMC_EVAL_FP64 = 0, ZMC_EVAL_FP32 = 1 } zmc_eval;
 
 /* result.flags */
 #define ZMC_F_TRUNCATED 1 /* a level would have exceeded max_cubes_per_level:
                              the cubes selected there were accepted instead */
 #define ZMC_F_RTOL_MET 2  /* the search stopped because stderr <= rtol*|I|  */
+#define ZMC_F_FP32_RANGE 4 /* ZMC_EVAL_FP32: in some cube the FP32 values lay
+                              below FP32's normal range (a sampling unit's
+                              values summed to less than its points times
+                              2^-126 in magnitude, after the per-cube scaling
+                              described at zmc_eval), so the tree and the
+                              result may differ from FP64 evaluation beyond
+                              rounding: evaluate this integrand in FP64 */
 
 /* Result of one integration.  integral, std and stderr_ are NaN unless
  * status is ZMC_OK; the per-level fields cover the levels that ran. */
@@ -175,7 +187,9 @@ typedef struct {
                                lane 0 uses serve_stream, the others streams
                                the library creates, each on a hardware queue
                                of its own); 0 = default 2, max 8              */
-    int32_t reserved;
+    int32_t default_eval;   /* zmc_eval of zmc_integrate() (the requests of
+                               the other entry points carry their own);
+                               0 = ZMC_EVAL_FP64                              */
     int64_t serve_chunk_samples; /* serving splits a level's sampling into
                                launches of about this many samples, so that
                                lanes share the device between launches;
@@ -203,7 +217,8 @@ typedef struct {
 
 /* Initialise the library on the current HIP device with the caller's arena.
  * EINVAL: NULL cfg/arena, arena_bytes < 64 MiB, misaligned arena,
- * serve_lanes outside 0..8, serve_chunk_samples < -1.
+ * serve_lanes outside 0..8, serve_chunk_samples < -1, default_eval not a
+ * zmc_eval.
  * Calling it again after zmc_shutdown() is allowed. */
 int zmc_init(const zmc_config* cfg);
 
@@ -211,20 +226,29 @@ int zmc_init(const zmc_config* cfg);
  * host staging memory.  The arena is not touched. */
 int zmc_shutdown(void);
 
-/* Integrate one function (Sec. 2.1 steps 1-6 above), synchronously.
- * params: n_params FP64 values (layout per zmc_integrand); lower/upper: dim
- * FP64 values each; out: caller memory, valid when ZMC_OK is returned (and
- * filled with status on ZMC_ENONFINITE / ZMC_ENOMEM).
- * EINVAL when: dim not in 1..16; lower_i >= upper_i or not finite; d < 1;
+/* Integrate one function (Sec. 2.1 steps 1-6 above), synchronously, with
+ * the user parameters of Sec. 2.3: the k = d^D root sub-domains
+ * (divisions_per_axis), the points per trial (samples_per_cube), the trials,
+ * the maximal partition depth (max_depth refinements after the roots) and the
+ * threshold multiplier (sigma_mult).
+ * params: FP64 values, as many as the integrand's layout above takes for dim
+ * (a run-time compiled integrand: the n_params it was registered with);
+ * lower/upper: dim FP64 values each; the evaluation mode is the
+ * configuration's default_eval; splits bisect every axis, one threshold per
+ * level, level cap 2^24 cubes (zmc_integrate_request() sets all of these).
+ * out: caller memory, valid when ZMC_OK is returned (and filled with status
+ * on ZMC_ENONFINITE / ZMC_ENOMEM).
+ * EINVAL when: params NULL where the layout takes values, lower/upper NULL;
+ * dim not in 1..16; lower_i >= upper_i or not finite; d < 1;
  * N < 1 or N*D > 2^34; trials not in 2..255; max_depth not in 0..15;
- * sigma_mult < 0 or not finite; unknown integrand or wrong n_params; a
- * MONOMIAL exponent outside 0..16 or not an integer; d^D * (b^D)^max_depth
- * > 2^64 (uid overflow; b = 2 unless the request sets split); d^D >
- * max_cubes_per_level; split or threshold_scope out of range.
+ * sigma_mult < 0 or not finite; unknown integrand; a MONOMIAL exponent
+ * outside 0..16 or not an integer; d^D * (b^D)^max_depth > 2^64 (uid
+ * overflow; b = 2 unless the request sets split); d^D > max_cubes_per_level;
+ * split or threshold_scope out of range.
  * ENOMEM when a level does not fit the arena. */
-int zmc_integrate(int integrand_id, const double* params, int n_params, int dim, const double* lower,
-                  const double* upper, int divisions_per_axis, int64_t samples_per_cube, int trials,
-                  int max_depth, double sigma_mult, uint64_t seed, int eval, void* stream, zmc_result* out);
+int zmc_integrate(int integrand_id, const double* params, int dim, const double* lower, const double* upper,
+                  int divisions_per_axis, int64_t samples_per_cube, int trials, int max_depth, double sigma_mult,
+                  uint64_t seed, void* stream, zmc_result* out);
 
 /* zmc_integrate() with every field of zmc_request (rtol, level cap) and an
  * optional trace (NULL = none). */

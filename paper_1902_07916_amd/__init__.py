@@ -21,12 +21,12 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from . import _abi
-from ._abi import (CONST, EVAL_FP32, EVAL_FP64, F_RTOL_MET, F_TRUNCATED, GAUSS, GENZ_CPEAK, GENZ_GAUSS,
+from ._abi import (CONST, EVAL_FP32, EVAL_FP64, F_FP32_RANGE, F_RTOL_MET, F_TRUNCATED, GAUSS, GENZ_CPEAK, GENZ_GAUSS,
                    GENZ_OSC, GENZ_PPEAK, INTEGRANDS, MONOMIAL, SIN_SUM, ZmcError, check)
 
 __all__ = ["Integrator", "Result", "make_request", "register_integrand", "ZmcError", "INTEGRANDS", "GAUSS", "SIN_SUM", "GENZ_OSC",
            "GENZ_PPEAK", "GENZ_CPEAK", "GENZ_GAUSS", "CONST", "MONOMIAL", "EVAL_FP64", "EVAL_FP32",
-           "F_TRUNCATED", "F_RTOL_MET"]
+           "F_TRUNCATED", "F_RTOL_MET", "F_FP32_RANGE"]
 
 
 def _integrand_id(x) -> int:
@@ -135,7 +135,8 @@ class Integrator:
     serving lanes, each an engine with its own thread, stream and equal share
     of the serving arena (0 = the library's default of 2);
     serve_chunk_samples: samples per sampling launch in serving (0 = the
-    library's default, -1 = one launch per level).  The library holds
+    library's default, -1 = one launch per level); default_eval: the
+    evaluation mode of the scalar zmc_integrate entry point.  The library holds
     one context per process: opening an Integrator closes the one open before
     it, whose calls then raise."""
 
@@ -143,7 +144,7 @@ class Integrator:
 
     def __init__(self, arena_bytes: int = 4 << 30, serve: bool = False, max_slots: int = 0, queue_depth: int = 0,
                  tune_path: str | None = None, device: int = 0, serve_lanes: int = 0,
-                 serve_chunk_samples: int = 0):
+                 serve_chunk_samples: int = 0, default_eval="fp64"):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("Integrator needs a ROCm GPU (torch.cuda.is_available() is False)")
@@ -160,6 +161,7 @@ class Integrator:
         cfg.serve_stream = self.serve_stream.cuda_stream if serve else None
         cfg.serve_lanes = int(serve_lanes)
         cfg.serve_chunk_samples = int(serve_chunk_samples)
+        cfg.default_eval = _eval_id(default_eval)
         self._tune = tune_path.encode() if tune_path else None
         cfg.tune_path = self._tune
         if Integrator._active is not None and Integrator._active is not self:

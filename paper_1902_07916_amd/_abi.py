@@ -24,7 +24,7 @@ INTEGRANDS = {"gauss": GAUSS, "sin_sum": SIN_SUM, "genz_osc": GENZ_OSC, "genz_pp
               "genz_cpeak": GENZ_CPEAK, "genz_gauss": GENZ_GAUSS, "const": CONST, "monomial": MONOMIAL}
 # zmc_eval
 EVAL_FP64, EVAL_FP32 = 0, 1
-F_TRUNCATED, F_RTOL_MET = 1, 2
+F_TRUNCATED, F_RTOL_MET, F_FP32_RANGE = 1, 2, 4
 
 EXPORTS = ("zmc_init", "zmc_shutdown", "zmc_integrate", "zmc_integrate_request", "zmc_integrate_batch",
            "zmc_submit", "zmc_poll", "zmc_cancel", "zmc_serve_stats", "zmc_debug_philox", "zmc_debug_points",
@@ -59,7 +59,7 @@ class Config(C.Structure):
     _fields_ = [
         ("arena", C.c_void_p), ("arena_bytes", C.c_uint64), ("max_slots", C.c_int32),
         ("queue_depth", C.c_int32), ("serve_stream", C.c_void_p), ("tune_path", C.c_char_p),
-        ("serve_lanes", C.c_int32), ("reserved", C.c_int32), ("serve_chunk_samples", C.c_int64),
+        ("serve_lanes", C.c_int32), ("default_eval", C.c_int32), ("serve_chunk_samples", C.c_int64),
     ]
 
 
@@ -89,8 +89,8 @@ def load(path: str = LIB_PATH):
     R, Q = C.POINTER(Result), C.POINTER(Request)
     L.zmc_init.argtypes = [C.POINTER(Config)]
     L.zmc_shutdown.argtypes = []
-    L.zmc_integrate.argtypes = [i32, C.POINTER(dbl), i32, i32, C.POINTER(dbl), C.POINTER(dbl), i32, i64, i32,
-                                i32, dbl, u64, i32, vp, R]
+    L.zmc_integrate.argtypes = [i32, C.POINTER(dbl), i32, C.POINTER(dbl), C.POINTER(dbl), i32, i64, i32, i32, dbl,
+                                u64, vp, R]
     L.zmc_integrate_request.argtypes = [Q, vp, R, C.POINTER(Trace)]
     L.zmc_integrate_batch.argtypes = [Q, i32, vp, R]
     L.zmc_submit.argtypes = [Q, C.POINTER(u64)]

@@ -74,6 +74,7 @@ struct Context {
     TileTable tiles;
     Engine sync_eng;
     std::mutex sync_mu;
+    int default_eval = ZMC_EVAL_FP64; // evaluation mode of zmc_integrate()
     Server* server = nullptr;
     // zmc_integrate_noalloc: a one-integral engine over the device scratch
     Engine static_eng;
@@ -93,7 +94,6 @@ constexpr size_t kStaticScratchBytes = size_t(64) << 20;
 static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
 constexpr int kMaxDevices = 64;
 void* g_scratch_ptr[kMaxDevices] = {};
-
 
 uint64_t ipow_sat(uint64_t b, int e, bool* ovf)
 {
@@ -369,6 +369,8 @@ int zmc_init(const zmc_config* cfg)
     if (((uintptr_t)cfg->arena & 255) != 0) return fail(ZMC_EINVAL, "zmc_init: arena must be 256-byte aligned");
     if (cfg->serve_lanes < 0 || cfg->serve_lanes > 8) return fail(ZMC_EINVAL, "zmc_init: serve_lanes must be in 0..8");
     if (cfg->serve_chunk_samples < -1) return fail(ZMC_EINVAL, "zmc_init: serve_chunk_samples must be >= -1");
+    if (cfg->default_eval != ZMC_EVAL_FP64 && cfg->default_eval != ZMC_EVAL_FP32)
+        return fail(ZMC_EINVAL, "zmc_init: default_eval must be a zmc_eval");
     if (g.inited) {
         stop_server();
         g.sync_eng.teardown();
@@ -377,6 +379,7 @@ int zmc_init(const zmc_config* cfg)
     }
     if (hipGetDevice(&g.device) != hipSuccess) return fail(ZMC_EDEVICE, "hipGetDevice failed");
     g.tiles = TileTable();
+    g.default_eval = cfg->default_eval;
     if (cfg->tune_path && cfg->tune_path[0]) {
         if (g.tiles.load(cfg->tune_path) != 0) return fail(ZMC_EINVAL, "zmc_init: cannot read tune_path");
     }
@@ -518,13 +521,20 @@ int zmc_integrate_noalloc(const zmc_request* req, void* stream, zmc_result* out)
     return rc;
 }
 
-int zmc_integrate(int integrand_id, const double* params, int n_params, int dim, const double* lower,
-                  const double* upper, int divisions_per_axis, int64_t samples_per_cube, int trials, int max_depth,
-                  double sigma_mult, uint64_t seed, int eval, void* stream, zmc_result* out)
+int zmc_integrate(int integrand_id, const double* params, int dim, const double* lower, const double* upper,
+                  int divisions_per_axis, int64_t samples_per_cube, int trials, int max_depth, double sigma_mult,
+                  uint64_t seed, void* stream, zmc_result* out)
 {
+    if (out) init_result(*out);
+    // the params layout of the registry (or of the registration) for dim
+    const int n_params = integrand_id >= kUserBase ? rtc_n_params(integrand_id) : n_params_of(integrand_id, dim);
+    if (n_params < 0) {
+        if (out) out->status = ZMC_EINVAL;
+        return fail(ZMC_EINVAL, "unknown integrand");
+    }
     if ((n_params > 0 && !params) || !lower || !upper) return fail(ZMC_EINVAL, "NULL params or bounds");
     const zmc_request r = make_request(integrand_id, params, n_params, dim, lower, upper, divisions_per_axis,
-                                       samples_per_cube, trials, max_depth, sigma_mult, seed, eval);
+                                       samples_per_cube, trials, max_depth, sigma_mult, seed, g.default_eval);
     return zmc_integrate_request(&r, stream, out, nullptr);
 }
 

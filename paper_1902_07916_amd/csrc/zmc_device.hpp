@@ -76,7 +76,7 @@ struct alignas(16) TileRec {
 enum Decision : int32_t { kSplit = 0, kDone = 1, kTruncated = 2, kRtolMet = 3 };
 
 // Arguments of one sampling launch (one (integrand, D, eval) bucket).
-constexpr int kSampleThreads = 256;
+constexpr int kSampleThreads = 256; // the largest sampling block (launch bound); 64 and 128 are tunable
 
 struct SampleArgs {
     const SlotDesc* slots;
@@ -88,7 +88,15 @@ struct SampleArgs {
     int64_t total_units; // units of this launch
     const uint64_t* uid;
     double2* partial;
+    int32_t* seg_flags;  // per segment of the level (0 at the level's start):
+                         // kRangeLost when an FP32 unit's sum fell below
+                         // FP32's normal range
 };
+
+// seg_flags / SegStats::range_lost: some sampling unit's FP32 values summed
+// to less than (points of the unit) * 2^-126 in magnitude, i.e. they lay
+// below FP32's normal range.
+constexpr int32_t kRangeLost = 1;
 
 // Per-segment outcome of one level, read back by the host after every level.
 struct alignas(16) SegStats {
@@ -97,6 +105,7 @@ struct alignas(16) SegStats {
     double totM, totS2; // running totals of the integral after this level
     int64_t n_sel;
     int32_t decision, nonfinite;
+    int32_t range_lost, pad;
 };
 
 // ---------------------------------------------------------------------------

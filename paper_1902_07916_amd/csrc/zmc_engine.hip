@@ -41,10 +41,12 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 // pays an L2 write-back to publish its tile record).
 constexpr int64_t kFuseMaxTiles = 256;
 
-// Packed per-level tables: segments at 0, running totals, bucket segments.
+// Packed per-level tables: segments at 0, running totals, bucket segments,
+// per-segment flags (uploaded as zeros).
 size_t prev_offset(int ns) { return align256((size_t)ns * sizeof(Segment)); }
 size_t bseg_offset(int ns) { return prev_offset(ns) + align256((size_t)ns * sizeof(double2)); }
-size_t table_bytes(int max_segs) { return bseg_offset(max_segs) + (size_t)max_segs * sizeof(BSeg); }
+size_t flags_offset(int ns) { return bseg_offset(ns) + align256((size_t)ns * sizeof(BSeg)); }
+size_t table_bytes(int max_segs) { return flags_offset(max_segs) + (size_t)max_segs * sizeof(int32_t); }
 
 // Built-in occupancy variant per bucket (index into kWaveHints), measured by
 // the tuner on gfx950 and embedded at build time; a tuning file overrides it.
@@ -54,6 +56,14 @@ int default_wave_hint(int f, int d, int e)
 {
     if (f < 0 || f >= 8 || d < 1 || d > ZMC_MAX_DIM || e < 0 || e > 1) return 0;
     return kDefaultWaveHint[f][d][e] < kNumWaveHints ? kDefaultWaveHint[f][d][e] : 0;
+}
+
+int valid_block(int b) { return b == 64 || b == 128 || b == 256; }
+
+int default_block(int f, int d, int e)
+{
+    if (f < 0 || f >= 8 || d < 1 || d > ZMC_MAX_DIM || e < 0 || e > 1) return kSampleThreads;
+    return valid_block(kDefaultBlock[f][d][e]) ? kDefaultBlock[f][d][e] : kSampleThreads;
 }
 
 // parts per axis when a cube is split (0 in a request means bisection)
@@ -83,13 +93,16 @@ TileTable::TileTable()
             for (int e = 0; e < 2; ++e) {
                 groups[f][d][e] = kDefaultGroups;
                 hint[f][d][e] = default_wave_hint(f, d, e);
+                threads[f][d][e] = default_block(f, d, e);
             }
 }
 
 // Tuning file: a JSON object whose keys "integrand:dim:eval" map to the
-// number of 4-point groups per thread per chunk, e.g. {"1:6:1": 8}, and whose
+// number of 4-point groups per thread per chunk, e.g. {"1:6:1": 8}, whose
 // keys "integrand:dim:eval:w" map to the minimum waves per SIMD of the
-// occupancy variant (one of kWaveHints), e.g. {"1:6:1:w": 8}.
+// occupancy variant (one of kWaveHints), e.g. {"1:6:1:w": 8}, and whose keys
+// "integrand:dim:eval:b" map to the threads per sampling block (64, 128 or
+// 256), e.g. {"1:6:1:b": 128}.
 int TileTable::load(const char* path)
 {
     std::ifstream in(path);
@@ -115,6 +128,7 @@ int TileTable::load(const char* path)
         if (nf == 4 && w == 'w')
             for (int h = 0; h < kNumWaveHints; ++h)
                 if (kWaveHints[h] == g) hint[f][d][e] = h;
+        if (nf == 4 && w == 'b' && valid_block(g)) threads[f][d][e] = g;
     }
     return 0;
 }
@@ -204,15 +218,15 @@ int Engine::groups_of(const zmc_request& r) const { return groups_for(r, *tiles_
 
 int Engine::nch_of(const zmc_request& r) const { return chunks_for(r, *tiles_); }
 
-int Engine::capacity(int integrand, int dim, int eval, bool keep_s2)
+int Engine::capacity(int integrand, int dim, int eval, bool keep_s2, int block)
 {
     const int hint = keep_s2 ? kSumsVariant : tiles_->waves(integrand, dim, eval);
-    const int key = (integrand * 1000 + dim * 2 + eval) * (kNumWaveHints + 1) + hint;
+    const int key = ((integrand * 1000 + dim * 2 + eval) * (kNumWaveHints + 1) + hint) * 8 + block / 64;
     auto it = cap_cache_.find(key);
     if (it != cap_cache_.end()) return it->second;
     int nb = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, sample_kernel_ptr(integrand, dim, eval, hint),
-                                                                kSampleThreads, 0);
+                                                                block, 0);
     if (e != hipSuccess || nb < 1) nb = 1;
     const int cap = nb * std::max(n_cu_, 1);
     cap_cache_[key] = cap;
@@ -302,6 +316,7 @@ void Engine::record_level(HostSlot& hs, const SegStats& S, int64_t n, double ms,
     if (S.decision == kTruncated) R.flags |= ZMC_F_TRUNCATED;
     if (S.decision == kRtolMet) R.flags |= ZMC_F_RTOL_MET;
     if (S.nonfinite) R.status = ZMC_ENONFINITE;
+    if (S.range_lost) R.flags |= ZMC_F_FP32_RANGE;
 }
 
 void Engine::finish(HostSlot& hs)
@@ -431,7 +446,11 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
         L.units = u;
         launches.push_back(L);
     }
-    ZMC_HIP(hipMemcpyAsync(d_tab_, h_tab_, bseg_offset(ns) + (size_t)nb * sizeof(BSeg), hipMemcpyHostToDevice, st));
+    int32_t* h_flags = (int32_t*)(h_tab_ + flags_offset(ns));
+    int32_t* d_flags = (int32_t*)(d_tab_ + flags_offset(ns));
+    memset(h_flags, 0, (size_t)ns * sizeof(int32_t));
+    ZMC_HIP(hipMemcpyAsync(d_tab_, h_tab_, flags_offset(ns) + (size_t)ns * sizeof(int32_t), hipMemcpyHostToDevice,
+                           st));
     ZMC_HIP(hipEventRecord(ev_sample0_, st));
     int n_launch = 0;
     for (const Launch& L : launches) {
@@ -443,6 +462,7 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
         a.n_bsegs = L.count;
         a.uid = cur_uid;
         a.partial = partial;
+        a.seg_flags = d_flags;
         // one launch, or launches of at most chunk_samples_ samples each
         int64_t chunk = L.units;
         if (chunk_samples_ > 0) chunk = std::max<int64_t>(1, chunk_samples_ / L.unit_samples);
@@ -453,10 +473,11 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
                 const int rc = rtc_launch(L.integrand, L.dim, L.eval, st, a);
                 if (rc != ZMC_OK) return rc;
             } else {
-                const int64_t cap = capacity(L.integrand, L.dim, L.eval, sums);
-                const int grid = (int)std::min<int64_t>(a.total_units, cap);
+                const int block = tiles_->block(L.integrand, L.dim, L.eval);
+                const int64_t cap = capacity(L.integrand, L.dim, L.eval, sums, block);
+                const int grid = (int)std::min<int64_t>(ceil_div(a.total_units, block / 64), cap);
                 const int hint = sums ? kSumsVariant : tiles_->waves(L.integrand, L.dim, L.eval);
-                ZMC_HIP(launch_sample(L.integrand, L.dim, L.eval, hint, grid, st, a));
+                ZMC_HIP(launch_sample(L.integrand, L.dim, L.eval, hint, grid, block, st, a));
             }
             ++n_launch;
         }
@@ -483,6 +504,7 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
     la.n_groups = groups;
     la.seg_count = d_seg_count_;
     la.host_stats = stats_only ? nullptr : d_hstats_;
+    la.seg_flags = d_flags;
     // small levels fold the per-segment steps into the tile kernels
     la.fused = tile <= kFuseMaxTiles ? 1 : 0;
     ZMC_HIP(launch_finalize(la, st));

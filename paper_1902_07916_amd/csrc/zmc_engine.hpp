@@ -67,13 +67,16 @@ private:
 };
 
 // Tile shape of the sampling kernel per (integrand, dim, eval): the cap on
-// 4-point groups per lane per chunk (default 32; a chunk is one wave's unit)
-// and the occupancy variant.  Fixed per build or tuning file, never by the
-// batch composition, so a request's result does not depend on its company
-// (the occupancy variant does not change any arithmetic at all).
+// 4-point groups per lane per chunk (default 32; a chunk is one wave's unit),
+// the occupancy variant and the block shape (threads per block: 64, 128 or
+// 256).  Fixed per build or tuning file, never by the batch composition, so
+// a request's result does not depend on its company (the group cap sets how
+// a trial's points are split into units; the occupancy variant and the block
+// shape change no arithmetic at all).
 struct TileTable {
     int groups[8][ZMC_MAX_DIM + 1][2];
-    int hint[8][ZMC_MAX_DIM + 1][2]; // index into kWaveHints
+    int hint[8][ZMC_MAX_DIM + 1][2];    // index into kWaveHints
+    int threads[8][ZMC_MAX_DIM + 1][2]; // threads per sampling block
     TileTable();
     int load(const char* path); // 0 on success
     int get(int integrand, int dim, int eval) const
@@ -84,6 +87,10 @@ struct TileTable {
     int waves(int integrand, int dim, int eval) const
     {
         return (integrand >= 0 && integrand < 8) ? hint[integrand][dim][eval] : 0;
+    }
+    int block(int integrand, int dim, int eval) const
+    {
+        return (integrand >= 0 && integrand < 8) ? threads[integrand][dim][eval] : kSampleThreads;
     }
     static constexpr int kDefaultGroups = 32;
 };
@@ -162,7 +169,7 @@ private:
              bool stats_only, bool want_sums);
     int next_list(hipStream_t st, std::vector<LiveSeg>& live, const std::vector<int>& split,
                   const std::vector<LiveSeg>& fresh, uint64_t*& cur_uid, int& cur_side);
-    int capacity(int integrand, int dim, int eval, bool keep_s2);
+    int capacity(int integrand, int dim, int eval, bool keep_s2, int block);
     void record_level(HostSlot& hs, const SegStats& S, int64_t n, double ms, float sample_ms, int launches);
     void finish(HostSlot& hs);
 

@@ -41,6 +41,7 @@ struct LevelArgs {
     int64_t n_groups;
     int32_t* seg_count;      // per segment: tile blocks done (0 between kernels)
     SegStats* host_stats;    // optional mapped host copy of the decisions
+    const int32_t* seg_flags; // per segment: flags the sampling launches raised
 };
 
 struct RootArgs {
@@ -61,7 +62,10 @@ constexpr int kNumWaveHints = 4;
 // squares (traced levels); it runs at the compiler's default occupancy
 constexpr int kSumsVariant = kNumWaveHints;
 
-hipError_t launch_sample(int integrand, int dim, int eval, int hint, int grid, hipStream_t st, const SampleArgs& a);
+// block: threads per sampling block, 64, 128 or 256 (whole waves; results
+// do not depend on it: every unit is one wave's work)
+hipError_t launch_sample(int integrand, int dim, int eval, int hint, int grid, int block, hipStream_t st,
+                         const SampleArgs& a);
 const void* sample_kernel_ptr(int integrand, int dim, int eval, int hint);
 hipError_t launch_finalize(const LevelArgs& a, hipStream_t st);
 hipError_t launch_threshold(const LevelArgs& a, hipStream_t st);
@@ -76,7 +80,8 @@ hipError_t launch_debug_points(const SlotDesc* sd, int level, uint64_t uid, int 
 
 // Per-integrand launch tables (one translation unit per integrand).
 #define ZMC_DECLARE_SAMPLE(F)                                                                              \
-    hipError_t launch_sample_##F(int dim, int eval, int hint, int grid, hipStream_t st, const SampleArgs& a); \
+    hipError_t launch_sample_##F(int dim, int eval, int hint, int grid, int block, hipStream_t st,               \
+                                 const SampleArgs& a);                                                             \
     const void* sample_kernel_ptr_##F(int dim, int eval, int hint);
 ZMC_DECLARE_SAMPLE(0)
 ZMC_DECLARE_SAMPLE(1)

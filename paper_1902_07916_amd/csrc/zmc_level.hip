@@ -474,6 +474,7 @@ __device__ void seg_decide(const LevelArgs& a, int si)
         S.selS2 = selS2;
         S.n_sel = nsel;
         S.nonfinite = bad;
+        S.range_lost = a.seg_flags ? a.seg_flags[si] : 0;
         int32_t dec;
         double totM = prev.x + accM, totS2 = prev.y + accS2;
         if (!sg.need_thr || nsel == 0) {
@@ -652,17 +653,18 @@ hipError_t launch_debug_points(const SlotDesc* sd, int level, uint64_t uid, int 
     return hipGetLastError();
 }
 
-hipError_t launch_sample(int integrand, int dim, int eval, int hint, int grid, hipStream_t st, const SampleArgs& a)
+hipError_t launch_sample(int integrand, int dim, int eval, int hint, int grid, int block, hipStream_t st,
+                         const SampleArgs& a)
 {
     switch (integrand) {
-    case 0: return launch_sample_0(dim, eval, hint, grid, st, a);
-    case 1: return launch_sample_1(dim, eval, hint, grid, st, a);
-    case 2: return launch_sample_2(dim, eval, hint, grid, st, a);
-    case 3: return launch_sample_3(dim, eval, hint, grid, st, a);
-    case 4: return launch_sample_4(dim, eval, hint, grid, st, a);
-    case 5: return launch_sample_5(dim, eval, hint, grid, st, a);
-    case 6: return launch_sample_6(dim, eval, hint, grid, st, a);
-    case 7: return launch_sample_7(dim, eval, hint, grid, st, a);
+    case 0: return launch_sample_0(dim, eval, hint, grid, block, st, a);
+    case 1: return launch_sample_1(dim, eval, hint, grid, block, st, a);
+    case 2: return launch_sample_2(dim, eval, hint, grid, block, st, a);
+    case 3: return launch_sample_3(dim, eval, hint, grid, block, st, a);
+    case 4: return launch_sample_4(dim, eval, hint, grid, block, st, a);
+    case 5: return launch_sample_5(dim, eval, hint, grid, block, st, a);
+    case 6: return launch_sample_6(dim, eval, hint, grid, block, st, a);
+    case 7: return launch_sample_7(dim, eval, hint, grid, block, st, a);
     default: return hipErrorInvalidValue;
     }
 }

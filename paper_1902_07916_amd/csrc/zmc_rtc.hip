@@ -77,12 +77,14 @@ namespace zmc {
 // cell values v in [1, 2), x_i = (lo_i - h_i (1 - 2^-24)) + h_i v_i.
 template <int D>
 struct UserIntegrand {
+    static constexpr bool kRangeCheck = true;
     struct P64 {
         const double* prm;
     };
     struct P32 {
         float b[D], m[D];
         const double* prm;
+        double scale;
     };
     __device__ static void prep64(const SlotDesc& sd, P64& p) { p.prm = sd.params; }
     __device__ static double f64(const P64& p, const double* x) { return zmc_user::f<double>(x, p.prm); }
@@ -93,6 +95,7 @@ struct UserIntegrand {
             p.m[i] = (float)h[i];
         }
         p.prm = sd.params;
+        p.scale = 1.0;
     }
     __device__ static float f32(const P32& p, const float* v)
     {

@@ -48,11 +48,11 @@ const void* ptr_d(int eval, int hint)
 }
 
 template <int F, int D>
-hipError_t launch_d(int eval, int hint, int grid, hipStream_t st, const SampleArgs& a)
+hipError_t launch_d(int eval, int hint, int grid, int block, hipStream_t st, const SampleArgs& a)
 {
     SampleArgs arg = a;
     void* args[] = {&arg};
-    return hipLaunchKernel(ptr_d<F, D>(eval, hint), dim3(grid), dim3(kSampleThreads), args, 0, st);
+    return hipLaunchKernel(ptr_d<F, D>(eval, hint), dim3(grid), dim3(block), args, 0, st);
 }
 
 } // namespace
@@ -63,12 +63,12 @@ hipError_t launch_d(int eval, int hint, int grid, hipStream_t st, const SampleAr
 #define ZMC_DIM_CASES(X)                                                                                   \
     X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
-hipError_t ZMC_CAT(launch_sample_, ZMC_F)(int dim, int eval, int hint, int grid, hipStream_t st,
+hipError_t ZMC_CAT(launch_sample_, ZMC_F)(int dim, int eval, int hint, int grid, int block, hipStream_t st,
                                           const SampleArgs& a)
 {
     switch (dim) {
 #define X(d)                                                                                               \
-    case d: return launch_d<ZMC_F, d>(eval, hint, grid, st, a);
+    case d: return launch_d<ZMC_F, d>(eval, hint, grid, block, st, a);
         ZMC_DIM_CASES(X)
 #undef X
     default: return hipErrorInvalidValue;

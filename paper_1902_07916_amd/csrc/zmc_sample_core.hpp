@@ -13,10 +13,15 @@
 // wave-uniform (SGPRs).  Each lane sums f and f^2 in FP64 and the wave
 // reduces with a fixed butterfly, so a unit's partial sums depend only on the
 // unit and G.  The grid is persistent: wave w takes a contiguous range of
-// units, and only the first unit's segment is found by binary search.
+// units; only the first unit's segment is found by binary search and only
+// its position decoded by division, later units follow by increments, and
+// a cube's corner and integrand constants are formed once for all of its
+// units.
 //
 // An integrand class I provides P64 / P32 parameter blocks, prep64 / prep32
-// (per cube, from the slot descriptor and the cube corner) and f64 / f32.
+// (per cube, from the slot descriptor and the cube corner), f64 / f32, the
+// FP64 scale P32::scale that multiplies each FP32 unit sum, and kRangeCheck
+// (whether its FP32 values can fall below FP32's normal range).
 #pragma once
 
 #include "zmc_device.hpp"
@@ -147,6 +152,38 @@ struct BoolTag {
     static constexpr bool value = B;
 };
 
+// Per-cube state of the sampling loop: FP32 evaluation keeps the integrand's
+// cube-relative constants (formed in FP64 from the corner), FP64 evaluation
+// the corner and the edge lengths scaled by 2^-24 with the integrand's
+// constants.  Computed once per cube, for all of its (trial, chunk) units.
+template <class I, int D, bool FP32>
+struct CubeState;
+
+template <class I, int D>
+struct CubeState<I, D, true> {
+    typename I::P32 p;
+    __device__ __forceinline__ void set(const SlotDesc& sd, int level, uint64_t uid)
+    {
+        double lo[D], h[D];
+        corner<D>(sd, level, uid, lo, h);
+        I::prep32(sd, lo, h, p);
+    }
+};
+
+template <class I, int D>
+struct CubeState<I, D, false> {
+    typename I::P64 p;
+    double lo[D], h24[D];
+    __device__ __forceinline__ void set(const SlotDesc& sd, int level, uint64_t uid)
+    {
+        double h[D];
+        corner<D>(sd, level, uid, lo, h);
+#pragma unroll
+        for (int i = 0; i < D; ++i) h24[i] = ldexp(h[i], -24);
+        I::prep64(sd, p);
+    }
+};
+
 // KEEP_S2: also accumulate the sum of squares (only the per-(cube, trial)
 // trace reads it; the estimator uses the sums alone).  Without it the
 // partial's second member is 0.
@@ -155,12 +192,13 @@ struct BoolTag {
 template <class I, int D, bool FP32, bool KEEP_S2, int W = 1>
 __device__ __forceinline__ void sample_units(const SampleArgs& a)
 {
-    constexpr int kWaves = kSampleThreads / 64;
+    // blocks of 64, 128 or 256 threads (the tile table's block shape)
+    const int waves_per_block = (int)(blockDim.x >> 6);
     const int lane = threadIdx.x & 63;
     // the wave index is uniform over the wave: keep it (and all unit
     // bookkeeping derived from it) in scalar registers
-    const int64_t wave = (int64_t)blockIdx.x * kWaves + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t n_waves = (int64_t)gridDim.x * kWaves;
+    const int64_t wave = (int64_t)blockIdx.x * waves_per_block + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t n_waves = (int64_t)gridDim.x * waves_per_block;
     const int64_t U = a.total_units;
     const int64_t per = (U + n_waves - 1) / n_waves;
     int64_t u = a.unit0 + wave * per;
@@ -177,28 +215,47 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
         }
     }
 
-    for (; u < uend; ++u) {
-        while (bs + 1 < a.n_bsegs && a.bsegs[bs + 1].unit_base <= u) ++bs;
-        const Segment& sg = a.segs[a.bsegs[bs].seg];
-        const SlotDesc& sd = a.slots[sg.slot];
-        const int64_t local = u - a.bsegs[bs].unit_base;
-        const int nch = sd.nch;
-        const int64_t upc = (int64_t)sd.trials * nch;
-        const int64_t cl = local / upc;
+    // The wave's first unit is decoded by division; every later one follows
+    // by increments (chunk, then trial, then cube), and a new bucket segment
+    // is decoded afresh.  Units are [cube][trial][chunk] within a segment.
+    const Segment* sg = nullptr;
+    const SlotDesc* sd = nullptr;
+    int64_t local = 0, cl = 0;
+    int trial = 0, chunk = 0;
+    auto decode = [&]() {
+        sg = &a.segs[a.bsegs[bs].seg];
+        sd = &a.slots[sg->slot];
+        local = u - a.bsegs[bs].unit_base;
+        const int nch = sd->nch;
+        const int64_t upc = (int64_t)sd->trials * nch;
+        cl = local / upc;
         const int rem = (int)(local - cl * upc);
-        const int trial = rem / nch;
-        const int chunk = rem - trial * nch;
-        const uint64_t uid = a.uid[sg.cube_base + cl];
-        const int level = sg.level;
+        trial = rem / nch;
+        chunk = rem - trial * nch;
+    };
+    decode();
+    CubeState<I, D, FP32> cs;
+    uint64_t uid = 0;
+    bool fresh = true; // the cube's state is to be (re)computed
 
-        double lo[D], h[D];
-        corner<D>(sd, level, uid, lo, h);
+    for (; u < uend; ++u) {
+        if (bs + 1 < a.n_bsegs && a.bsegs[bs + 1].unit_base <= u) {
+            while (bs + 1 < a.n_bsegs && a.bsegs[bs + 1].unit_base <= u) ++bs;
+            decode();
+            fresh = true;
+        }
+        const int level = sg->level;
+        if (fresh) {
+            uid = a.uid[sg->cube_base + cl];
+            cs.set(*sd, level, uid);
+            fresh = false;
+        }
 
-        const uint32_t k0 = (uint32_t)sd.seed, k1 = (uint32_t)(sd.seed >> 32);
+        const uint32_t k0 = (uint32_t)sd->seed, k1 = (uint32_t)(sd->seed >> 32);
         const uint32_t c1 = (uint32_t)trial | ((uint32_t)level << 8);
         const uint32_t c2 = (uint32_t)uid, c3 = (uint32_t)(uid >> 32);
-        const int64_t N = sd.samples;
-        const int G = sd.groups;
+        const int64_t N = sd->samples;
+        const int G = sd->groups;
         const int64_t g0 = (int64_t)chunk * G * 64 + lane;
 
         double S1 = 0.0, S2 = 0.0;
@@ -211,73 +268,87 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
         // the allocator spill (up to 66% slower), and from D = kHalvesMinD
         // on the mask costs under 1%; those keep the one masked loop.
         constexpr bool kWholeLoop = D < kHalvesMinD && (W <= 5 || (W == 7 && D <= 6));
-        if constexpr (FP32) {
-            typename I::P32 p;
-            I::prep32(sd, lo, h, p);
-            auto run = [&](auto ragged) {
-                for (int j = 0; j < G; ++j) {
-                    const int64_t g = g0 + (int64_t)j * 64;
-                    const int64_t s0 = 4 * g;
-                    if (s0 >= N) break;
-                    int nvalid = 4;
-                    if constexpr (decltype(ragged)::value) nvalid = (int)min((int64_t)4, N - s0);
-                    group_samples<D>((uint32_t)g * (uint32_t)D, c1, c2, c3, k0, k1, [&](int q, const uint32_t* w) {
+        // A group's 4 values are summed in pairs, ((f0 + f1) + (f2 + f3)),
+        // before they join the running sum: one dependent FP64 add per group
+        // on the sum's chain instead of four.
+        auto run = [&](auto ragged) {
+            for (int j = 0; j < G; ++j) {
+                const int64_t g = g0 + (int64_t)j * 64;
+                const int64_t s0 = 4 * g;
+                if (s0 >= N) break;
+                int nvalid = 4;
+                if constexpr (decltype(ragged)::value) nvalid = (int)min((int64_t)4, N - s0);
+                double p01 = 0.0, pcur = 0.0, q01 = 0.0, qcur = 0.0;
+                auto add = [&](int q, double fd) {
+                    if (q == 0 || q == 2) {
+                        pcur = fd;
+                        if constexpr (KEEP_S2) qcur = fd * fd;
+                    } else {
+                        pcur += fd;
+                        if constexpr (KEEP_S2) qcur = fma(fd, fd, qcur);
+                        if (q == 1) {
+                            p01 = pcur;
+                            if constexpr (KEEP_S2) q01 = qcur;
+                        } else {
+                            S1 += p01 + pcur;
+                            if constexpr (KEEP_S2) S2 += q01 + qcur;
+                        }
+                    }
+                };
+                group_samples<D>((uint32_t)g * (uint32_t)D, c1, c2, c3, k0, k1, [&](int q, const uint32_t* w) {
+                    if constexpr (FP32) {
                         float v[D];
 #pragma unroll
                         for (int i = 0; i < D; ++i) v[i] = unit_interval_f32(w[i]);
-                        float f = I::f32(p, v);
+                        float f = I::f32(cs.p, v);
                         if constexpr (decltype(ragged)::value) f = (q < nvalid) ? f : 0.0f;
-                        const double fd = (double)f;
-                        S1 += fd;
-                        if constexpr (KEEP_S2) S2 = fma(fd, fd, S2);
-                    });
-                }
-            };
-            if constexpr (kWholeLoop) {
-                if ((N & 3) == 0) run(BoolTag<false>{});
-                else run(BoolTag<true>{});
-            } else {
-                run(BoolTag<true>{});
-            }
-        } else {
-            typename I::P64 p;
-            I::prep64(sd, p);
-            double h24[D];
-#pragma unroll
-            for (int i = 0; i < D; ++i) h24[i] = ldexp(h[i], -24);
-            auto run = [&](auto ragged) {
-                for (int j = 0; j < G; ++j) {
-                    const int64_t g = g0 + (int64_t)j * 64;
-                    const int64_t s0 = 4 * g;
-                    if (s0 >= N) break;
-                    int nvalid = 4;
-                    if constexpr (decltype(ragged)::value) nvalid = (int)min((int64_t)4, N - s0);
-                    group_samples<D>((uint32_t)g * (uint32_t)D, c1, c2, c3, k0, k1, [&](int q, const uint32_t* w) {
+                        add(q, (double)f);
+                    } else {
                         double x[D];
                         // x = fma(h, (2*(w>>9)+1) 2^-24, lo) computed as
                         // fma(h 2^-24, (w>>8)|1, lo): the same exact product
 #pragma unroll
-                        for (int i = 0; i < D; ++i) x[i] = fma(h24[i], (double)((w[i] >> 8) | 1u), lo[i]);
-                        double f = I::f64(p, x);
+                        for (int i = 0; i < D; ++i) x[i] = fma(cs.h24[i], (double)((w[i] >> 8) | 1u), cs.lo[i]);
+                        double f = I::f64(cs.p, x);
                         if constexpr (decltype(ragged)::value) f = (q < nvalid) ? f : 0.0;
-                        S1 += f;
-                        if constexpr (KEEP_S2) S2 = fma(f, f, S2);
-                    });
-                }
-            };
-            if constexpr (kWholeLoop) {
-                if ((N & 3) == 0) run(BoolTag<false>{});
-                else run(BoolTag<true>{});
-            } else {
-                run(BoolTag<true>{});
+                        add(q, f);
+                    }
+                });
             }
+        };
+        if constexpr (kWholeLoop) {
+            if ((N & 3) == 0) run(BoolTag<false>{});
+            else run(BoolTag<true>{});
+        } else {
+            run(BoolTag<true>{});
         }
 
         S1 = wave_sum(S1);
         if constexpr (KEEP_S2) S2 = wave_sum(S2);
+        if constexpr (FP32) {
+            if constexpr (I::kRangeCheck) {
+                // values below FP32's normal range: report it for the segment
+                const int64_t pts = min((int64_t)G * 256, N - (int64_t)chunk * G * 256);
+                if (lane == 0 && fabs(S1) < (double)pts * 0x1p-126)
+                    atomicOr(a.seg_flags + a.bsegs[bs].seg, kRangeLost);
+            }
+            S1 *= cs.p.scale;
+            if constexpr (KEEP_S2) S2 *= cs.p.scale * cs.p.scale;
+        }
         // partial sums in unit order, [cube][trial * nch + chunk]: a wave's
         // consecutive units fill whole cache lines
-        if (lane == 0) a.partial[sg.part_base + local] = make_double2(S1, S2);
+        if (lane == 0) a.partial[sg->part_base + local] = make_double2(S1, S2);
+
+        // the next unit: chunk, then trial, then cube
+        ++local;
+        if (++chunk == sd->nch) {
+            chunk = 0;
+            if (++trial == sd->trials) {
+                trial = 0;
+                ++cl;
+                fresh = true;
+            }
+        }
     }
 }
 

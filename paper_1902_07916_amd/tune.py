@@ -2,13 +2,16 @@
 
     python -m paper_1902_07916_amd.tune --out tune.json [--dims 2-12] [--integrands genz_osc,...]
     python -m paper_1902_07916_amd.tune --waves --out tune.json --dims 1-16 --evals fp32,fp64
+    python -m paper_1902_07916_amd.tune --blocks --out tune.json --dims 1-16 --samples 4096
 
-For every (integrand, D, eval) bucket it times the sampling + per-cube
-reduction of a fixed list of root cubes (zmc_cube_estimates, N points per
-cube, 16384 unless --samples, 3 trials) for each candidate cap on the 4-point groups a thread takes per
-chunk (the chunk is 4 * 256 * groups points), and writes the fastest as a
+For every (integrand, D, eval) bucket it times the sampling launches of one
+level over the root cubes of [0,1]^D (N points per cube, 16384 unless
+--samples, 3 trials; HIP events on the launch stream, the fastest of 5 runs)
+for each candidate cap on the 4-point groups a thread takes per chunk (the
+chunk is 4 * 64 * groups points per wave), and writes the fastest as a
 JSON object {"integrand:dim:eval": groups, ...} that zmc_init() reads from
-`tune_path`.  The table depends only on the bucket, never on what else is
+`tune_path`.  --waves picks each bucket's occupancy variant and --blocks its
+block shape (threads per sampling block) by timing the sampling launches.  The table depends only on the bucket, never on what else is
 resident, so a request's result stays independent of its batch.
 """
 from __future__ import annotations
@@ -44,10 +47,11 @@ def _params(name: str, D: int):
     raise ValueError(name)
 
 
-def time_bucket(name: str, D: int, eval_: str, groups: int, n_cubes: int = 4096, reps: int = 3,
+def time_bucket(name: str, D: int, eval_: str, groups: int, n_cubes: int = 4096, reps: int = 5,
                 N: int = 16384) -> float:
-    """Seconds per sample of the sampling + reduction kernels with the given cap."""
-    import numpy as np
+    """Seconds per sample of the sampling launches with the given cap: one
+    level over d^D >= n_cubes root cubes (3 trials), the launches' HIP-event
+    time, the fastest of `reps` runs after a warm-up run."""
     import torch
     from paper_1902_07916_amd import INTEGRANDS, Integrator, make_request
     key = "%d:%d:%d" % (INTEGRANDS[name], D, 1 if eval_ == "fp32" else 0)
@@ -60,17 +64,11 @@ def time_bucket(name: str, D: int, eval_: str, groups: int, n_cubes: int = 4096,
         while d ** D < n_cubes and d < 64:
             d += 1
         req = make_request(name, _params(name, D), [0.0] * D, [1.0] * D, d, N, 3, 0, 1.0, 1, eval=eval_)
-        n = min(n_cubes, d ** D)
-        uids = np.arange(n, dtype=np.uint64)
-        zi.cube_estimates(req, 0, uids, sums=False)
+        zi.integrate_request(req)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            zi.cube_estimates(req, 0, uids, sums=False)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / reps
+        rs = [zi.integrate_request(req) for _ in range(reps)]
         zi.close()
-        return dt / (n * 3 * N)
+        return min(r.sample_ms_per_level[0] for r in rs) * 1e-3 / rs[0].n_samples
     finally:
         os.unlink(path)
 
@@ -160,6 +158,54 @@ def wave_sweep(out_path, evals=("fp32", "fp64"), dims=range(1, 17), n_target=163
     return best
 
 
+BLOCKS = (64, 128, 256)  # threads per sampling block
+
+
+def block_sweep(out_path, evals=("fp32",), dims=range(1, 17), n_target=65536, N=4096, trials=3):
+    """Time every block shape of every registry bucket (each in its built-in
+    occupancy variant) and write the fastest as {"integrand:dim:eval:b":
+    threads} (merged into out_path); 256 is kept unless another shape is
+    MIN_GAIN faster."""
+    from paper_1902_07916_amd import INTEGRANDS, Integrator
+    rates = {}
+    for b in BLOCKS:
+        table = {"%d:%d:%d:b" % (INTEGRANDS[n], D, 1 if ev == "fp32" else 0): b
+                 for n in REGISTRY for D in dims for ev in evals}
+        with tempfile.NamedTemporaryFile("w", suffix=".json", delete=False) as fh:
+            json.dump(table, fh)
+            path = fh.name
+        try:
+            zi = Integrator(arena_bytes=16 << 30, tune_path=path)
+            for ev in evals:
+                for name in REGISTRY:
+                    for D in dims:
+                        rates[(name, D, ev, b)] = _bucket_rate(zi, name, D, ev, n_target, N, trials)[1]
+                        print("b%d %s %-11s D=%2d %.3e samples/s" % (b, ev, name, D, rates[(name, D, ev, b)]),
+                              flush=True)
+            zi.close()
+        finally:
+            os.unlink(path)
+    best = json.load(open(out_path)) if os.path.exists(out_path) else {}
+    for ev in evals:
+        for name in REGISTRY:
+            for D in dims:
+                r = {b: rates[(name, D, ev, b)] for b in BLOCKS}
+                b_best = max(r, key=r.get)
+                if r[b_best] < MIN_GAIN * r[256]:
+                    b_best = 256
+                key = "%d:%d:%d:b" % (INTEGRANDS[name], D, 1 if ev == "fp32" else 0)
+                if b_best == 256:
+                    best.pop(key, None)
+                else:
+                    best[key] = b_best
+                print("%s %-11s D=%2d  %s  best %d (%.1f%% over 256)" % (
+                    ev, name, D, " ".join("b%d:%.3e" % (b, v) for b, v in r.items()), b_best,
+                    100 * (r[b_best] / r[256] - 1)), flush=True)
+    with open(out_path, "w") as fh:
+        json.dump(best, fh, indent=1, sort_keys=True)
+    return best
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=None)
@@ -171,9 +217,17 @@ def main(argv=None) -> int:
     ap.add_argument("--waves", action="store_true",
                     help="time every occupancy variant of every registry bucket; write the fastest to --out")
     ap.add_argument("--tune-path", default=None, help="tuning file for --table")
+    ap.add_argument("--blocks", action="store_true",
+                    help="time every block shape (64/128/256 threads) of every registry bucket; write the fastest "
+                         "to --out")
     a = ap.parse_args(argv)
     if a.table:
         rate_table(evals=a.evals.split(","), N=a.samples, tune_path=a.tune_path)
+        return 0
+    if a.blocks:
+        if not a.out:
+            ap.error("--blocks needs --out")
+        block_sweep(a.out, evals=a.evals.split(","), dims=_parse_dims(a.dims), N=a.samples)
         return 0
     if a.waves:
         if not a.out:

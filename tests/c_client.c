@@ -46,8 +46,8 @@ int main(void)
     const double lower[4] = {-1.0, -1.0, -1.0, -1.0};
     const double upper[4] = {1.0, 1.0, 1.0, 1.0};
     zmc_result r;
-    if (check(zmc_integrate(ZMC_GAUSS, params, 6, 4, lower, upper, 4, 4096, 5, 1, 1.0, 1, ZMC_EVAL_FP64, NULL, &r),
-              "zmc_integrate"))
+    /* cfg.default_eval = 0: FP64 evaluation */
+    if (check(zmc_integrate(ZMC_GAUSS, params, 4, lower, upper, 4, 4096, 5, 1, 1.0, 1, NULL, &r), "zmc_integrate"))
         return 1;
     printf("sync %.17g %.17g %d %llu\n", r.integral, r.std, r.levels_run, (unsigned long long)r.n_samples);
 

@@ -103,6 +103,9 @@ def test_init_rejects_bad_config(lib):
     cfg.serve_lanes = 0
     cfg.serve_chunk_samples = -2
     assert lib.zmc_init(C.byref(cfg)) == _abi.EINVAL
+    cfg.serve_chunk_samples = 0
+    cfg.default_eval = 2
+    assert lib.zmc_init(C.byref(cfg)) == _abi.EINVAL
 
 
 def test_integrate_scalar_entry_checks(lib):
@@ -110,10 +113,32 @@ def test_integrate_scalar_entry_checks(lib):
     out = _abi.Result()
     lo = (C.c_double * 2)(0.0, 0.0)
     hi = (C.c_double * 2)(1.0, 1.0)
-    rc = lib.zmc_integrate(1, None, 0, 2, lo, hi, 2, 16, 3, 1, 1.0, 1, 0, None, C.byref(out))
+    # sin(sum x) takes no params; the Gaussian takes 2 + D, derived from dim
+    rc = lib.zmc_integrate(_abi.SIN_SUM, None, 2, lo, hi, 2, 16, 3, 1, 1.0, 1, None, C.byref(out))
     assert rc == _abi.ENOINIT
-    rc = lib.zmc_integrate(1, None, 0, 2, None, hi, 2, 16, 3, 1, 1.0, 1, 0, None, C.byref(out))
+    prm = (C.c_double * 4)(0.2, 1.0, 0.5, 0.5)
+    rc = lib.zmc_integrate(_abi.GAUSS, prm, 2, lo, hi, 2, 16, 3, 1, 1.0, 1, None, C.byref(out))
+    assert rc == _abi.ENOINIT
+    rc = lib.zmc_integrate(_abi.GAUSS, None, 2, lo, hi, 2, 16, 3, 1, 1.0, 1, None, C.byref(out))
     assert rc == _abi.EINVAL
+    rc = lib.zmc_integrate(_abi.SIN_SUM, None, 2, None, hi, 2, 16, 3, 1, 1.0, 1, None, C.byref(out))
+    assert rc == _abi.EINVAL
+    rc = lib.zmc_integrate(42, None, 2, lo, hi, 2, 16, 3, 1, 1.0, 1, None, C.byref(out))
+    assert rc == _abi.EINVAL and out.status == _abi.EINVAL
+
+
+def test_integrate_has_the_documented_signature():
+    """zmc_integrate takes exactly (integrand_id, params, dim, lower, upper,
+    divisions_per_axis, samples_per_cube, trials, max_depth, sigma_mult,
+    seed, stream, out): the parameter count is derived from the integrand
+    and the evaluation mode comes from the configuration."""
+    text = open(os.path.join(ROOT, "include", "zmc.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    decl = re.search(r"int zmc_integrate\((.*?)\);", text, flags=re.S).group(1)
+    names = [re.split(r"[\s*]+", a.strip())[-1] for a in decl.split(",")]
+    assert names == ["integrand_id", "params", "dim", "lower", "upper", "divisions_per_axis", "samples_per_cube",
+                     "trials", "max_depth", "sigma_mult", "seed", "stream", "out"]
+    assert re.search(r"int32_t default_eval;", text)
 
 
 def test_workloads_are_deterministic():
