@@ -26,6 +26,10 @@
  *   oracle_integrate      pinned: closed forms within k*stderr, constant
  *                         integrand exact, Cantelli bound on selections,
  *                         paper's printed anchors (Tables 1, 2) as loose sanity.
+ *   sum_abs / per-cube sa pinned: equal to +-integral where f keeps one sign
+ *                         (refined, truncated and rtol-stopped trees), the
+ *                         closed forms of the integral of |sin| (1-D) and
+ *                         |sin(x + y)| (2-D) where it changes sign.
  *   exact tree shape at the large 6-D / 9-D workloads: parity unpinned beyond
  *   self-consistency (nothing external fixes it).
  */

@@ -18,7 +18,7 @@ import pytest
 
 sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
 import closed_forms as cf  # noqa: E402
-from common import margin_band_ok, oracle_problem, rel  # noqa: E402
+from common import check_levels_sampled, rel  # noqa: E402
 
 pytestmark = pytest.mark.gpu
 
@@ -37,41 +37,7 @@ def zi():
 def _check_levels(orc, w, r, n_sample, m_tol, m_floor=0.0):
     """m_floor: absolute slack for values FP32 cannot represent (a cube whose
     FP64 estimate is ~1e-200 reads 0 in FP32)."""
-    p = oracle_problem(orc, w)
-    D = len(w["lower"])
-    rng = np.random.default_rng(0)
-    M = S2 = 0.0
-    acc_m = []
-    acc_s2 = []
-    for l, L in enumerate(r.trace):
-        assert len(L["uid"]) == L["n"] == r.cubes_per_level[l]
-        # sampled cubes recomputed by the oracle
-        idx = np.unique(np.concatenate([[0, L["n"] - 1], rng.integers(0, L["n"], n_sample)]))
-        for i in idx:
-            st, I, m, s, sa = orc.cube(p, l, int(L["uid"][i]))
-            assert st == 0
-            assert abs(L["m"][i] - m) <= m_tol * sa + m_floor, (l, i, L["m"][i], m, sa)
-            assert abs(L["s"][i] - s) <= m_tol * sa * 10 + 1e-9 * s + m_floor, (l, i, L["s"][i], s)
-        if l < w["max_depth"] and l + 1 < len(r.trace):
-            thr, mu, sd = orc.threshold(L["s"], w["sigma_mult"])
-            assert rel(r.thr_per_level[l], thr) < 1e-12
-            band = margin_band_ok(L["s"], L["sel"], thr, 1e-12)
-            assert len(band) == 0, "cubes within 1e-12 of the threshold: %s" % band
-            assert int(L["sel"].sum()) == r.selected_per_level[l]
-            parents = L["uid"][L["sel"].astype(bool)]
-            kids = ((parents[:, None] << np.uint64(D)) | np.arange(2**D, dtype=np.uint64)[None, :]).ravel()
-            assert np.array_equal(r.trace[l + 1]["uid"], kids)
-            for j in rng.integers(0, len(parents), 4):
-                assert np.array_equal(orc.children(int(parents[j]), D), kids[j * 2**D:(j + 1) * 2**D])
-            keep = ~L["sel"].astype(bool)
-        else:
-            keep = np.ones(L["n"], bool)
-        acc_m.append(L["m"][keep])
-        acc_s2.append(L["s"][keep] ** 2)
-    M = math.fsum(np.concatenate(acc_m))
-    S2 = math.fsum(np.concatenate(acc_s2))
-    assert rel(r.integral, M) < 1e-10 or abs(r.integral - M) < 1e-12 * float(np.abs(np.concatenate(acc_m)).sum())
-    assert rel(r.std, math.sqrt(S2)) < 1e-10
+    check_levels_sampled(orc, w, r, n_sample, m_tol, m_floor)
 
 
 @pytest.mark.parametrize("eval_,tol", [("fp32", 2e-5), ("fp64", 1e-12)])
@@ -238,4 +204,59 @@ def test_fp32_sine_has_no_mean_error(zi):
     per_sum = float(np.sqrt(np.mean(diff ** 2))) / N / (2 / np.pi)
     print("FP32 sine: signed mean error %.3g of mean |f| over %.3g points; per-sum rms %.3g" % (mean_rel, n, per_sum))
     assert abs(mean_rel) < 1e-9
+    assert per_sum < 2e-6
+
+
+FP32_BIAS_CASES = [
+    # (integrand, params for D = 4, box): positive families, the integral of
+    # |f| is the integral of f
+    ("gauss", [0.3, 1.7, 0.2, 0.4, 0.6, 0.5], 0.0, 1.0),
+    ("genz_ppeak", [2.0, 4.0, 1.0, 3.0, 0.2, 0.7, 0.9, 0.4], 0.0, 1.0),
+    ("genz_cpeak", [0.9, 2.0, 3.5, 1.2], 0.0, 1.0),
+    ("genz_gauss", [1.0, 3.0, 0.5, 2.0, 0.2, 0.8, 0.5, 0.1], 0.0, 1.0),
+    ("monomial", [1.0, 2.0, 3.0, 4.0], 0.5, 1.5),
+]
+
+
+@pytest.mark.parametrize("name,prm,lo,hi", FP32_BIAS_CASES, ids=[c[0] for c in FP32_BIAS_CASES])
+def test_fp32_families_have_no_mean_error(zi, name, prm, lo, hi):
+    """FP32 evaluation of every positive registry family against FP64 on the
+    same 5e7 points (8^4 root cubes of a 4-D box, 3 trials of 4096 points):
+    the signed mean of (f32 - f64), relative to the mean of f, is below
+    1e-6 -- a systematic error far inside the 1e-4 tolerance of FP32-mode
+    results (measured: the FP32 rounding of the per-cube constants and the
+    hardware exp2 / rcp; see the design notes)."""
+    from paper_1902_07916_amd import make_request
+    d, D, N, n1 = 8, 4, 4096, 3
+    uids = np.arange(d ** D, dtype=np.uint64)
+    sums = []
+    for ev in ("fp32", "fp64"):
+        rq = make_request(name, prm, [lo] * D, [hi] * D, d, N, n1, 2, 1.0, 17, eval=ev)
+        sums.append(zi.cube_estimates(rq, 0, uids)[2])
+    diff = float(np.sum(sums[0] - sums[1]))
+    mean_rel = diff / float(np.sum(sums[1]))
+    per_sum = float(np.max(np.abs(sums[0] - sums[1]) / np.abs(sums[1])))
+    print("FP32 %s: signed mean error %.3g of mean f; largest per-sum error %.3g" % (name, mean_rel, per_sum))
+    assert abs(mean_rel) < 1e-6
+    assert per_sum < 2e-5
+
+
+def test_fp32_oscillatory_has_no_mean_error(zi):
+    """The oscillatory family (cos of a phase that sweeps many periods over
+    the box, so the mean of |f| is 2/pi): signed mean error of FP32 against
+    FP64 on the same 5e7 points below 1e-8 of mean |f|."""
+    from paper_1902_07916_amd import make_request
+    d, D, N, n1 = 8, 4, 4096, 3
+    prm = [0.3, 11.0, 17.5, 7.0, 23.0]
+    uids = np.arange(d ** D, dtype=np.uint64)
+    sums = []
+    for ev in ("fp32", "fp64"):
+        rq = make_request("genz_osc", prm, [0.0] * D, [1.0] * D, d, N, n1, 2, 1.0, 19, eval=ev)
+        sums.append(zi.cube_estimates(rq, 0, uids)[2])
+    diff = sums[0] - sums[1]
+    n = diff.size * N
+    mean_rel = float(np.sum(diff)) / n / (2 / np.pi)
+    per_sum = float(np.sqrt(np.mean(diff ** 2))) / N / (2 / np.pi)
+    print("FP32 genz_osc: signed mean error %.3g of mean |f|; per-sum rms %.3g" % (mean_rel, per_sum))
+    assert abs(mean_rel) < 1e-8
     assert per_sum < 2e-6

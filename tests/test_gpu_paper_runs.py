@@ -1,0 +1,108 @@
+"""The paper's own runs (Sec. 3, Tables 1-4) on the GPU against the oracle,
+at the paper's sub-domains per axis, partition depth and k-sigma cut, under
+both readings of the split (bisection of every axis; the literal d equal
+parts per axis), in FP64 and FP32 evaluation.
+
+ * Whole trees at reduced points per sub-domain (the oracle finishes in
+   seconds): lists bit-exact, per-(cube, trial) sums, per-cube estimates,
+   thresholds, selections and totals (decisions inside the rounding band
+   replayed).  The 9-D f2 runs use 1000 points, where the FP64 tree finds
+   the peak exactly as at the paper's 3^9 and 10^4.
+ * At the paper's own points per sub-domain: sampled cubes of every level
+   recomputed by the oracle, thresholds over the GPU's own s, selections,
+   child lists and totals.
+ * FP32 evaluation of f2 (sigma = 0.01): at the root level every sampled
+   value lies far below FP32's range (1e-290 and less), so the FP32 tree
+   cannot see the peak; the result must carry ZMC_F_FP32_RANGE."""
+import os
+import sys
+
+import pytest
+
+sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+from common import check_levels_sampled, compare_tree  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+EPS64 = 1e-9
+EPS32 = 1e-4
+
+# points per sub-domain for the whole-tree comparison (the paper's: 20^6,
+# 10^6, 10^4, 3^9, 10^4)
+REDUCED_N = {"f1_tf": 256, "f1_numba": 16, "f1_ray": 4, "f2_numba": 1000, "f2_ray": 1000}
+
+
+@pytest.fixture(scope="module")
+def zi():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1902_07916_amd import Integrator
+    z = Integrator(arena_bytes=16 << 30)
+    yield z
+    z.close()
+
+
+def _splits(name):
+    from paper_1902_07916_amd import workloads as W
+    r = W.PAPER_RUNS[name]
+    return [0] if r["max_depth"] == 0 else [0, r["divisions"]]
+
+
+def _cases(names, evals):
+    return [(n, s, e) for n in names for s in _splits(n) for e in evals]
+
+
+WHOLE = _cases(["f1_tf", "f1_numba", "f1_ray"], ("fp64", "fp32")) + _cases(["f2_numba", "f2_ray"], ("fp64",))
+
+
+@pytest.mark.parametrize("name,split,eval_", WHOLE, ids=["%s-split%d-%s" % c for c in WHOLE])
+def test_paper_run_whole_tree(zi, orc, name, split, eval_):
+    from paper_1902_07916_amd import F_FP32_RANGE
+    from paper_1902_07916_amd import workloads as W
+    w = W.paper_run(name, eval=eval_, seed=1, split=split)
+    w["samples"] = REDUCED_N[name]
+    print("paper run %s split=%d %s: N=%d" % (name, split, eval_, w["samples"]), flush=True)
+    r = zi.integrate(**w, trace=True, trace_capacity=3 << 20)
+    assert r.status == 0 and not r.flags & F_FP32_RANGE
+    if W.PAPER_RUNS[name]["f"] == "f2":
+        # the peak's cube is selected at every level below the last
+        assert all(n >= 1 for n in r.selected_per_level[:-1]) and r.levels_run == w["max_depth"] + 1
+    o = compare_tree(orc, w, r, EPS64 if eval_ == "fp64" else EPS32, 1e-6 if eval_ == "fp64" else 1e-4)
+    if eval_ == "fp64":
+        assert all(L.n_in_band == 0 for L in o.levels)
+    print("  levels %s, integral %.6g (oracle %.6g)" % (r.cubes_per_level, r.integral, o.integral))
+
+
+FULL = _cases(["f1_numba", "f1_ray"], ("fp64", "fp32")) + _cases(["f2_ray", "f2_12d_ray"], ("fp64",))
+
+
+@pytest.mark.parametrize("name,split,eval_", FULL, ids=["%s-split%d-%s" % c for c in FULL])
+def test_paper_run_full_size_sampled(zi, orc, name, split, eval_):
+    from paper_1902_07916_amd import F_FP32_RANGE
+    from paper_1902_07916_amd import workloads as W
+    w = W.paper_run(name, eval=eval_, seed=1, split=split)
+    print("paper run %s split=%d %s at N=%d" % (name, split, eval_, w["samples"]), flush=True)
+    r = zi.integrate(**w, trace=True, trace_capacity=3 << 20)
+    assert r.status == 0 and not r.flags & F_FP32_RANGE
+    # per cube: the oracle's N * trials points for the sampled cubes
+    n_sample = 4 if w["samples"] >= 10 ** 6 else 24
+    check_levels_sampled(orc, w, r, n_sample, 1e-12 if eval_ == "fp64" else 2e-5)
+    print("  levels %s, selected %s, integral %.6g +- %.3g" % (r.cubes_per_level, r.selected_per_level,
+                                                             r.integral, r.stderr))
+
+
+@pytest.mark.parametrize("name", ["f2_numba", "f2_ray", "f2_12d_ray"])
+def test_paper_f2_fp32_reports_range_loss(zi, name):
+    """At the paper's parameters the FP64 tree selects the peak's cube at
+    the root level; FP32 evaluation cannot represent those values, selects
+    nothing, and says so."""
+    from paper_1902_07916_amd import F_FP32_RANGE
+    from paper_1902_07916_amd import workloads as W
+    split = W.PAPER_RUNS[name]["divisions"]
+    r64 = zi.integrate(**W.paper_run(name, eval="fp64", seed=1, split=split))
+    r32 = zi.integrate(**W.paper_run(name, eval="fp32", seed=1, split=split))
+    print("%s: fp64 %.6g levels %s; fp32 %.6g flags %d" % (name, r64.integral, r64.cubes_per_level, r32.integral,
+                                                           r32.flags), flush=True)
+    assert r64.status == 0 and r64.selected_per_level[0] >= 1 and not r64.flags & F_FP32_RANGE
+    assert r32.status == 0 and r32.flags & F_FP32_RANGE

@@ -123,3 +123,61 @@ def test_paper_anchor_f2(orc):
     # normalised f2 (sigma = 0.01, 9-D, [-1,1]^9) integrates to 1 (Sec. 3)
     A = (2 * math.pi) ** -4.5 / 0.01**9
     assert cf.gauss(0.01, A, [0.0] * 9, [-1.0] * 9, [1.0] * 9) == pytest.approx(1.0, rel=1e-12)
+
+
+# ---- the oracle's estimate of the integral of |f| (sum_abs) ------------------
+# It scales the parity tolerances of integrals near zero, so it is pinned on
+# its own: where f keeps one sign it must equal +-integral (the same points,
+# summed in another order), and where f changes sign it must approach the
+# closed form of the integral of |f|.
+
+def test_sum_abs_equals_integral_for_a_positive_integrand(orc):
+    # refined tree (accepted cubes from three levels), asymmetric box
+    p = orc.problem(orc.GAUSS, 3, [-1.0, -0.5, 0.0], [1.0, 1.5, 0.5], 3, 512, 4, 2, 0.5, 3,
+                    params=[0.4, 2.0, 0.1, 0.3, 0.2])
+    r = orc.integrate(p)
+    assert r.status == 0 and len(r.levels) == 3 and r.levels[1].n_sel > 0
+    assert r.sum_abs == pytest.approx(r.integral, rel=1e-13)
+    for L in r.levels:
+        np.testing.assert_allclose(L.sa, L.m, rtol=1e-13)
+    # the same under the truncation rule (the selected cubes of the last
+    # level are accepted) and the rtol stop
+    for kw in (dict(max_cubes_per_level=100), dict(rtol=0.01)):
+        p2 = orc.problem(orc.GAUSS, 3, [-1.0, -0.5, 0.0], [1.0, 1.5, 0.5], 3, 512, 4, 2, 0.5, 3,
+                         params=[0.4, 2.0, 0.1, 0.3, 0.2], **kw)
+        r2 = orc.integrate(p2)
+        assert r2.flags != 0
+        assert r2.sum_abs == pytest.approx(r2.integral, rel=1e-13)
+
+
+def test_sum_abs_equals_minus_integral_for_a_negative_integrand(orc):
+    # sin(x + y) with x + y in [3.2, 6.2], inside (pi, 2 pi): f < 0 everywhere
+    p = orc.problem(orc.SIN_SUM, 2, [1.6, 1.6], [3.1, 3.1], 4, 300, 3, 1, 1.0, 8)
+    r = orc.integrate(p)
+    assert r.status == 0 and r.integral < 0
+    assert r.sum_abs == pytest.approx(-r.integral, rel=1e-13)
+
+
+def test_sum_abs_matches_closed_form_where_f_changes_sign(orc):
+    # 1-D: integral of |sin x| over [0, 3 pi / 2] is 3 (the integral of sin is 1)
+    p = orc.problem(orc.SIN_SUM, 1, 0.0, 1.5 * math.pi, 64, 16384, 3, 0, 1.0, 2)
+    r = orc.integrate(p)
+    assert r.integral == pytest.approx(1.0, abs=1e-3)
+    assert r.sum_abs == pytest.approx(3.0, abs=1e-4)
+    # 2-D: x + y over [0, pi]^2 has the triangular density on [0, 2 pi], so
+    # the integral of |sin(x + y)| is 2 pi (and that of sin(x + y) is 0)
+    p = orc.problem(orc.SIN_SUM, 2, 0.0, math.pi, 16, 8192, 3, 0, 1.0, 4)
+    r = orc.integrate(p)
+    assert r.integral == pytest.approx(0.0, abs=1e-3)
+    assert r.sum_abs == pytest.approx(2.0 * math.pi, rel=1e-4)
+    # per cube: where sin(x + y) keeps one sign the estimate is |m|; in a cube
+    # that straddles x + y = pi (uid 120: x + y in [15 pi/16, 17 pi/16]) it is
+    # the cube's integral of |f| (midpoint sum), to its sampling error
+    for uid in (0, 7, 255):
+        st, I, m, s, sa = orc.cube(p, 0, uid)
+        assert sa == pytest.approx(abs(m), rel=1e-13), uid
+    st, I, m, s, sa = orc.cube(p, 0, 120)
+    clo, h, _ = orc.bounds(p, 0, 120)
+    ref = _riemann_2d(lambda x, y: np.abs(np.sin(x + y)), clo, clo + h, n=512)
+    assert abs(m) < 0.2 * ref
+    assert sa == pytest.approx(ref, rel=3e-2)
