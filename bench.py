@@ -57,9 +57,12 @@ def valu_instructions_per_sample(integrand: str, D: int, eval_: str) -> dict:
             # back on (copysign, an integer bit-field insert)
             fp32 += 11
             ints += 1
-        elif integrand in ("gauss", "genz_gauss"):
-            fp32 += D + 2          # t^2 sum, scale, A *
-            trans += 1             # exp2
+        elif integrand == "gauss":
+            fp32 += D + 1          # t^2 sum (from the cube's minimum), scale
+            trans += 1             # exp2 (the amplitude multiplies the unit's FP64 sum)
+        elif integrand == "genz_gauss":
+            fp32 += D              # t^2 sum (from the cube's minimum)
+            trans += 1             # exp2 of the negated sum (a source modifier)
         elif integrand == "genz_ppeak":
             fp32 += 2 * D
             trans += 1             # rcp
@@ -131,12 +134,61 @@ def measured_traffic(workload: str):
     return e["bytes_per_launch"]
 
 
-def cpu_baseline(w: dict, seconds: float) -> dict:
-    """The CPU oracle as it stands, single thread, on the first root cubes of
-    the same workload (all trials, all points), until `seconds` elapse."""
+def _oracle_problem(w: dict):
     import oracle
-    p = oracle.problem(w["integrand"], len(w["lower"]), w["lower"], w["upper"], w["divisions"], w["samples"],
-                       w["trials"], w["max_depth"], w["sigma_mult"], w["seed"], params=w["params"])
+    return oracle.problem(w["integrand"], len(w["lower"]), w["lower"], w["upper"], w["divisions"], w["samples"],
+                          w["trials"], w["max_depth"], w["sigma_mult"], w["seed"], params=w["params"],
+                          rtol=w.get("rtol", 0.0), max_cubes_per_level=w.get("max_cubes_per_level", 0) or (1 << 24),
+                          split=w.get("split", 0) or 2)
+
+
+def _oracle_cubes(args):
+    """Worker of the all-core leg: oracle.cube on root cubes first, first +
+    stride, ... until `seconds` elapse; returns (cubes, seconds)."""
+    w, first, stride, seconds = args
+    import oracle
+    p = _oracle_problem(w)
+    t0 = time.perf_counter()
+    n = 0
+    c = first
+    while time.perf_counter() - t0 < seconds:
+        oracle.cube(p, 0, c)
+        c += stride
+        n += 1
+    return n, time.perf_counter() - t0
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_cores() -> int:
+    """Cores this process may use, capped at 16 (the host share of one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_baseline(w: dict, seconds: float, small: dict | None = None) -> dict:
+    """The CPU oracle as it stands (plain single-thread FP64 C), timed on this
+    host: single thread on the first root cubes of the same workload (all
+    trials, all points) until `seconds` elapse; the same per-cube work spread
+    over the host's cores by a process pool (cube c to worker c mod P); and,
+    if given, the whole tree of a small workload in one thread."""
+    import multiprocessing as mp
+
+    import oracle
+    oracle.build()
+    p = _oracle_problem(w)
     t0 = time.perf_counter()
     n = 0
     while time.perf_counter() - t0 < seconds:
@@ -144,9 +196,27 @@ def cpu_baseline(w: dict, seconds: float) -> dict:
         n += 1
     dt = time.perf_counter() - t0
     samples = n * w["trials"] * w["samples"]
-    return {"value": samples / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
-            "sample": "level-0 cubes 0..%d of the same workload, %d trials x %d points each (%.3g samples, %.1f s)"
-                      % (n - 1, w["trials"], w["samples"], samples, dt)}
+    out = {"value": samples / dt, "unit": "samples/s", "cores": 1, "kind": "oracle",
+           "sample": "level-0 cubes 0..%d of the same workload, %d trials x %d points each (%.3g samples, %.1f s)"
+                     % (n - 1, w["trials"], w["samples"], samples, dt),
+           "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    P = host_cores()
+    with mp.get_context("spawn").Pool(P) as pool:
+        res = pool.map(_oracle_cubes, [(w, i, P, seconds) for i in range(P)])
+    n_all = sum(r[0] for r in res)
+    t_all = max(r[1] for r in res)
+    out["all_cores"] = {"value": n_all * w["trials"] * w["samples"] / t_all, "unit": "samples/s", "cores": P,
+                        "sample": "level-0 cubes of the same workload, cube c on worker c mod %d, %.1f s" % (P, t_all)}
+    if small is not None:
+        ps = _oracle_problem(small)
+        t0 = time.perf_counter()
+        o = oracle.integrate(ps)
+        dt = time.perf_counter() - t0
+        out["small_whole_tree"] = {"value": o.n_samples / dt, "unit": "samples/s", "cores": 1, "s": dt,
+                                   "samples": o.n_samples, "integral": o.integral,
+                                   "sample": "the whole tree of the 4-D Gaussian workload (256 roots, 4096 points, "
+                                             "5 trials, one refinement) in one thread"}
+    return out
 
 
 def percentile(xs, q):
@@ -159,48 +229,58 @@ def percentile(xs, q):
     return xs[f] + (xs[c] - xs[f]) * (k - f)
 
 
-def run_batch(a) -> dict:
+def run_batch(a, steps=None, warmup=None) -> dict:
     """Batched workload: n independent Genz integrals (D in 2..12) per step,
     all levels of all of them in shared launches."""
     import torch
     from paper_1902_07916_amd import INTEGRANDS, Integrator, request_from_dict, workloads
+    steps = a.steps if steps is None else steps
+    warmup = a.warmup if warmup is None else warmup
     ws = workloads.genz_batch(n=a.batch_n, max_cubes_per_level=a.batch_cap)
     reqs = [request_from_dict(w) for w in ws]
     zi = Integrator(arena_bytes=int(a.arena_gib * (1 << 30)), max_slots=max(8192, len(reqs)))
-    for _ in range(a.warmup):
+    for _ in range(warmup):
         zi.integrate_batch(reqs)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    outs = [zi.integrate_batch(reqs) for _ in range(a.steps)]
+    outs = [zi.integrate_batch(reqs) for _ in range(steps)]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     zi.close()
+    a_steps = steps
     last = outs[-1]
     samples = sum(r.n_samples for o in outs for r in o)
     # minimal VALU instructions of the last step: every sample of every level
     names = {v: k for k, v in INTEGRANDS.items()}
     instr = 0.0
+    int_instr = 0.0
     for w, r in zip(ws, last):
-        per = valu_instructions_per_sample(names[w["integrand"]], len(w["lower"]), w["eval"])["total"]
-        instr += per * sum(int(c) for c in r.cubes_per_level[:r.levels_run]) * w["trials"] * w["samples"]
+        n = valu_instructions_per_sample(names[w["integrand"]], len(w["lower"]), w["eval"])
+        pts = sum(int(c) for c in r.cubes_per_level[:r.levels_run]) * w["trials"] * w["samples"]
+        instr += n["total"] * pts
+        int_instr += (n["int"] + n["fp64"]) * pts
     # sampling-kernel time of the last step: integrals stepped together
     # share one launch set per level, whose HIP-event time every one of them
     # records; count each (level, time) once
     k_ms = sum(ms for _, ms in {(l, float(r.sample_ms_per_level[l])) for r in last for l in range(r.levels_run)})
-    return {"integrals_per_s": len(reqs) * a.steps / dt, "samples_per_s": samples / dt,
-            "ms_per_step": dt * 1e3 / a.steps, "n_integrals": len(reqs),
+    return {"integrals_per_s": len(reqs) * a_steps / dt, "samples_per_s": samples / dt,
+            "ms_per_step": dt * 1e3 / a_steps, "steps": a_steps, "warmup": warmup, "n_integrals": len(reqs),
             "status_ok": sum(r.status == 0 for r in last), "truncated": sum(bool(r.flags & 1) for r in last),
-            "cubes_total": sum(r.n_cubes for r in last), "samples_per_step": samples // a.steps,
+            "fp32_range": sum(bool(r.flags & 4) for r in last),
+            "cubes_total": sum(r.n_cubes for r in last), "samples_per_step": samples // a_steps,
             "sample_kernel_ms_per_step": k_ms,
             "alu_frac_sampling": instr / (k_ms * 1e-3) / VALU_PEAK if k_ms > 0 else None,
-            "alu_frac_wall": instr / (dt / a.steps) / VALU_PEAK}
+            "int_issue_frac_sampling": (int_instr / (k_ms * 1e-3) / (N_CU * CLOCK_HZ * INT_LANES_PER_CU_CLK)
+                                        if k_ms > 0 else None),
+            "alu_frac_wall": instr / (dt / a_steps) / VALU_PEAK}
 
 
-def run_serve(a) -> dict:
+def run_serve(a, duration=None) -> dict:
     """Serving workload: a Poisson stream of requests submitted in real time;
     latency = submit -> result visible to poll."""
     from paper_1902_07916_amd import Integrator, request_from_dict, workloads
-    stream = workloads.serving_stream(rate=a.rate, duration=a.duration)
+    duration = a.duration if duration is None else duration
+    stream = workloads.serving_stream(rate=a.rate, duration=duration)
     reqs = [request_from_dict(w) for _, w in stream]
     zi = Integrator(arena_bytes=int(a.arena_gib * (1 << 30)), serve=True)
     # warm the kernels of every (integrand, D) bucket once
@@ -220,11 +300,11 @@ def run_serve(a) -> dict:
     st = zi.serve_stats()
     zi.close()
     lat = [r.latency_ms for r in res]
-    return {"requests": len(res), "offered_rate": a.rate, "duration_s": a.duration, "wall_s": dt,
+    return {"requests": len(res), "offered_rate": a.rate, "duration_s": duration, "wall_s": dt,
             "integrals_per_s": len(res) / dt, "p50_ms": percentile(lat, 0.5), "p99_ms": percentile(lat, 0.99),
             "max_ms": max(lat), "rtol_met": sum(bool(r.flags & 2) for r in res) / len(res),
             "status_ok": sum(r.status == 0 for r in res), "samples": sum(r.n_samples for r in res),
-            "levels_stepped": st["levels"]}
+            "samples_per_s": sum(r.n_samples for r in res) / dt, "levels_stepped": st["levels"]}
 
 
 # The paper's own timings on its hardware (Tables 1-4), seconds per run.
@@ -285,7 +365,11 @@ def main(argv=None) -> int:
     ap.add_argument("--workload", default="sin6d", choices=sorted(WORKLOADS))
     ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "paper"])
     ap.add_argument("--no-fp64", action="store_true", help="skip timing the plain FP64 path")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=8.0)
+    ap.add_argument("--batch-steps", type=int, default=1,
+                    help="timed steps of the batched leg in the default run (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
+                    help="length of the serving leg's request stream in the default run (0 = skip)")
     ap.add_argument("--arena-gib", type=float, default=48.0)
     ap.add_argument("--batch-n", type=int, default=4096)
     ap.add_argument("--batch-cap", type=int, default=1 << 20)
@@ -368,18 +452,36 @@ def main(argv=None) -> int:
         out["result"]["z"] = (r.integral - exact) / r.stderr
 
     if not a.no_fp64:
+        # the plain FP64 path, warmed and timed exactly like the FP32 one
+        for _ in range(a.warmup):
+            zi.integrate(**w64)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r64 = zi.integrate(**w64)
+        res64 = [zi.integrate(**w64) for _ in range(a.steps)]
         torch.cuda.synchronize()
         dt64 = time.perf_counter() - t0
-        out["fp64_path"] = {"value": r64.n_samples / dt64, "unit": "samples/s", "ms_per_step": dt64 * 1e3,
+        r64 = res64[-1]
+        v64 = sum(x.n_samples for x in res64) / dt64
+        k64 = sum(sum(x.sample_ms_per_level) for x in res64)
+        out["fp64_path"] = {"value": v64, "unit": "samples/s", "ms_per_step": dt64 * 1e3 / a.steps,
+                            "steps": a.steps, "warmup": a.warmup,
+                            "kernel_samples_per_s": sum(x.n_samples for x in res64) / (k64 * 1e-3),
                             "integral": r64.integral, "stderr": r64.stderr, "levels": r64.cubes_per_level,
-                            "speedup_fp32_over_fp64": value / (r64.n_samples / dt64),
+                            "speedup_fp32_over_fp64": value / v64,
                             "rel_diff_fp32_vs_fp64": abs(r.integral - r64.integral) / abs(r64.integral)}
     zi.close()
+    if a.batch_steps > 0:
+        print("bench: batched leg", file=sys.stderr, flush=True)
+        out["batch"] = {"workload": "4096 Genz integrals, D in 2..12, N=4096, n1=3, max_depth=2, sigma_mult=5, "
+                                    "seed=7, level cap 2^20, FP32 evaluation", **run_batch(a, a.batch_steps, 1)}
+    if a.serve_seconds > 0:
+        print("bench: serving leg", file=sys.stderr, flush=True)
+        out["serving"] = {"workload": "Poisson %.0f requests/s for %.0f s, Genz integrals D in 3..12, rtol "
+                                      "10^U(-5,-3), seed=11" % (a.rate, a.serve_seconds),
+                          **run_serve(a, a.serve_seconds)}
     if a.cpu_seconds > 0:
-        out["cpu_baseline"] = cpu_baseline(w64, a.cpu_seconds)
+        print("bench: CPU oracle leg", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w64, a.cpu_seconds, small=workloads.gauss4d(eval="fp64"))
     print(json.dumps(out))
     return 0
 
