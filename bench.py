@@ -283,9 +283,15 @@ def run_serve(a, duration=None) -> dict:
     stream = workloads.serving_stream(rate=a.rate, duration=duration)
     reqs = [request_from_dict(w) for _, w in stream]
     zi = Integrator(arena_bytes=int(a.arena_gib * (1 << 30)), serve=True)
-    # warm the kernels of every (integrand, D) bucket once
+    # warm the kernels of every (integrand, D) bucket once; then the cost of
+    # a level beyond its sampling launches: the first 200 requests run
+    # alone, wall time per level minus the sampling launches' HIP-event time
     for rq in reqs[:64]:
         zi.integrate_request(rq)
+    over = []
+    for rq in reqs[:200]:
+        r = zi.integrate_request(rq)
+        over += [m - s for m, s in zip(r.ms_per_level, r.sample_ms_per_level)]
     t0 = time.perf_counter()
     tickets = []
     for (t, _), rq in zip(stream, reqs):
@@ -304,7 +310,9 @@ def run_serve(a, duration=None) -> dict:
             "integrals_per_s": len(res) / dt, "p50_ms": percentile(lat, 0.5), "p99_ms": percentile(lat, 0.99),
             "max_ms": max(lat), "rtol_met": sum(bool(r.flags & 2) for r in res) / len(res),
             "status_ok": sum(r.status == 0 for r in res), "samples": sum(r.n_samples for r in res),
-            "samples_per_s": sum(r.n_samples for r in res) / dt, "levels_stepped": st["levels"]}
+            "samples_per_s": sum(r.n_samples for r in res) / dt, "levels_stepped": st["levels"],
+            "level_cost_beyond_sampling_ms": {"p50": percentile(over, 0.5), "p90": percentile(over, 0.9),
+                                              "levels": len(over)}}
 
 
 # The paper's own timings on its hardware (Tables 1-4), seconds per run.

@@ -14,9 +14,10 @@
  *     estimates I_t = V * mean_s f(x_s) are formed, each from
  *     `samples_per_cube` points.  Point s, dimension i of trial t in the cube
  *     (uid, level) uses word n = s*D + i of the Philox4x32-10 stream with key
- *     = seed and counter (n >> 2, t | level << 8, lo32(uid), hi32(uid)), lane
- *     n & 3; the word w maps to u = (2*(w >> 9) + 1) * 2^-24 and
- *     x_i = fma(h_i, u, lo_i).
+ *     = seed and counter (n >> 2, t | level << 8 | uid_hi << 12, lo32(uid),
+ *     hi32(uid)), lane n & 3, where a cube id has up to 84 bits, uid holding
+ *     bits 0..63 and uid_hi bits 64..83; the word w maps to
+ *     u = (2*(w >> 9) + 1) * 2^-24 and x_i = fma(h_i, u, lo_i).
  *  3. Per cube: m = mean of the I_t, s = population std of the I_t.
  *  4. Per level and per integral: thr = mean(s) + sigma_mult * std(s)
  *     (population std); a cube with s > thr is split (unless the level is
@@ -199,8 +200,9 @@ typedef struct {
 /* Per-level trace of a synchronous integration (test and debugging hook).
  * For every level l < max_levels the library copies up to `capacity`
  * entries, in list order, into the caller's host buffers (any may be NULL):
- * uid[l][c], m[l][c], s[l][c], sel[l][c] (1 = split) and, per trial,
- * S1[l][c*trials + t] = sum f and S2[l][c*trials + t] = sum f^2.
+ * uid[l][c] (cube id bits 0..63), m[l][c], s[l][c], sel[l][c] (1 = split)
+ * and, per trial, S1[l][c*trials + t] = sum f and S2[l][c*trials + t] =
+ * sum f^2; uid_hi[l][c] receives id bits 64..83 (0 below 2^64).
  * n[l] receives the number of cubes at level l (even if > capacity). */
 typedef struct {
     int32_t max_levels;
@@ -213,6 +215,7 @@ typedef struct {
     uint8_t* sel[ZMC_MAX_LEVELS];
     double* S1[ZMC_MAX_LEVELS];
     double* S2[ZMC_MAX_LEVELS];
+    uint32_t* uid_hi[ZMC_MAX_LEVELS];
 } zmc_trace;
 
 /* Initialise the library on the current HIP device with the caller's arena.
@@ -242,9 +245,10 @@ int zmc_shutdown(void);
  * dim not in 1..16; lower_i >= upper_i or not finite; d < 1;
  * N < 1 or N*D > 2^34; trials not in 2..255; max_depth not in 0..15;
  * sigma_mult < 0 or not finite; unknown integrand; a MONOMIAL exponent
- * outside 0..16 or not an integer; d^D * (b^D)^max_depth > 2^64 (uid
- * overflow; b = 2 unless the request sets split); d^D > max_cubes_per_level;
- * split or threshold_scope out of range.
+ * outside 0..16 or not an integer; d^D * (b^D)^max_depth > 2^84 (cube ids
+ * hold 84 bits; b = 2 unless the request sets split) or d * b^max_depth >
+ * 2^64 (lattice cells per axis); d^D > max_cubes_per_level; split or
+ * threshold_scope out of range.
  * ENOMEM when a level does not fit the arena. */
 int zmc_integrate(int integrand_id, const double* params, int dim, const double* lower, const double* upper,
                   int divisions_per_axis, int64_t samples_per_cube, int trials, int max_depth, double sigma_mult,

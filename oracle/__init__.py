@@ -60,8 +60,19 @@ class Replay(C.Structure):
         ("n_levels", C.c_int32),
         ("n", C.c_int64 * MAX_LEVELS),
         ("uid", C.POINTER(C.c_uint64) * MAX_LEVELS),
+        ("uid_hi", C.POINTER(C.c_uint32) * MAX_LEVELS),
         ("sel", C.POINTER(C.c_uint8) * MAX_LEVELS),
     ]
+
+
+ID_BITS = 84  # cube ids: bits 0..63 in uid, 64..83 in uid_hi
+
+
+def _split_id(uid):
+    uid = int(uid)
+    if uid < 0 or uid >> ID_BITS:
+        raise ValueError("cube id out of range")
+    return uid & ((1 << 64) - 1), uid >> 64
 
 
 _lib = None
@@ -78,6 +89,21 @@ def lib():
         L.oracle_uniform.restype = C.c_double
         L.oracle_word.argtypes = [C.c_uint64, C.c_uint64, C.c_int, C.c_int, C.c_int, C.c_int64, C.c_int]
         L.oracle_word.restype = C.c_uint32
+        L.oracle_word_w.argtypes = [C.c_uint64, C.c_uint64, C.c_uint32, C.c_int, C.c_int, C.c_int, C.c_int64,
+                                    C.c_int]
+        L.oracle_word_w.restype = C.c_uint32
+        L.oracle_cube_lattice_w.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_uint32,
+                                            C.POINTER(C.c_uint64)]
+        L.oracle_cube_bounds_w.argtypes = [P, C.c_int, C.c_uint64, C.c_uint32, C.POINTER(C.c_double),
+                                           C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.oracle_sample_x_w.argtypes = [P, C.c_int, C.c_uint64, C.c_uint32, C.c_int, C.c_int64,
+                                        C.POINTER(C.c_double)]
+        L.oracle_cube_trial_w.argtypes = [P, C.c_int, C.c_uint64, C.c_uint32, C.c_int, C.POINTER(C.c_double),
+                                          C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.oracle_cube_w.argtypes = [P, C.c_int, C.c_uint64, C.c_uint32, C.POINTER(C.c_double),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.oracle_children_w.argtypes = [C.c_uint64, C.c_uint32, C.c_int, C.c_int, C.POINTER(C.c_uint64),
+                                        C.POINTER(C.c_uint32)]
         L.oracle_cube_lattice.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, C.c_uint64, C.POINTER(C.c_uint64)]
         L.oracle_cube_bounds.argtypes = [P, C.c_int, C.c_uint64, C.POINTER(C.c_double),
                                          C.POINTER(C.c_double), C.POINTER(C.c_double)]
@@ -102,7 +128,8 @@ def lib():
         L.oracle_run_totals.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
         L.oracle_level_n.argtypes = [C.c_void_p, C.c_int]
         L.oracle_level_n.restype = C.c_int64
-        for name, t in (("oracle_level_uid", C.c_uint64), ("oracle_level_m", C.c_double),
+        for name, t in (("oracle_level_uid", C.c_uint64), ("oracle_level_uid_hi", C.c_uint32),
+                        ("oracle_level_m", C.c_double),
                         ("oracle_level_s", C.c_double), ("oracle_level_I", C.c_double),
                         ("oracle_level_sa", C.c_double), ("oracle_level_sel", C.c_uint8)):
             f = getattr(L, name)
@@ -183,12 +210,15 @@ def uniform(w: int) -> float:
 
 
 def word(seed, uid, level, trial, dim, s, i) -> int:
-    return lib().oracle_word(int(seed), int(uid), int(level), int(trial), int(dim), int(s), int(i))
+    """uid: a cube id of up to 84 bits (a Python int)."""
+    lo, hi = _split_id(uid)
+    return lib().oracle_word_w(int(seed), lo, hi, int(level), int(trial), int(dim), int(s), int(i))
 
 
 def lattice(dim, divisions, level, uid, split=2):
     K = (C.c_uint64 * MAX_DIM)()
-    lib().oracle_cube_lattice(dim, divisions, split, level, int(uid), K)
+    lo, hi = _split_id(uid)
+    lib().oracle_cube_lattice_w(dim, divisions, split, level, lo, hi, K)
     return np.array(K[:dim], dtype=np.uint64)
 
 
@@ -196,7 +226,8 @@ def bounds(p: Problem, level: int, uid: int):
     lo = (C.c_double * MAX_DIM)()
     h = (C.c_double * MAX_DIM)()
     v = C.c_double()
-    lib().oracle_cube_bounds(C.byref(p), level, int(uid), lo, h, C.byref(v))
+    a, b = _split_id(uid)
+    lib().oracle_cube_bounds_w(C.byref(p), level, a, b, lo, h, C.byref(v))
     return np.array(lo[:p.dim]), np.array(h[:p.dim]), v.value
 
 
@@ -208,21 +239,24 @@ def f(integrand, params, x) -> float:
 
 def sample_x(p: Problem, level, uid, trial, s):
     x = (C.c_double * MAX_DIM)()
-    lib().oracle_sample_x(C.byref(p), level, int(uid), trial, int(s), x)
+    a, b = _split_id(uid)
+    lib().oracle_sample_x_w(C.byref(p), level, a, b, trial, int(s), x)
     return np.array(x[:p.dim])
 
 
 def cube_trial(p: Problem, level, uid, trial):
     I, S1, S2, SA = C.c_double(), C.c_double(), C.c_double(), C.c_double()
-    st = lib().oracle_cube_trial(C.byref(p), level, int(uid), trial, C.byref(I), C.byref(S1),
-                                 C.byref(S2), C.byref(SA))
+    a, b = _split_id(uid)
+    st = lib().oracle_cube_trial_w(C.byref(p), level, a, b, trial, C.byref(I), C.byref(S1), C.byref(S2),
+                                   C.byref(SA))
     return st, I.value, S1.value, S2.value, SA.value
 
 
 def cube(p: Problem, level, uid):
     I = (C.c_double * p.trials)()
     m, s, sa = C.c_double(), C.c_double(), C.c_double()
-    st = lib().oracle_cube(C.byref(p), level, int(uid), I, C.byref(m), C.byref(s), C.byref(sa))
+    a, b = _split_id(uid)
+    st = lib().oracle_cube_w(C.byref(p), level, a, b, I, C.byref(m), C.byref(s), C.byref(sa))
     return st, np.array(I[:]), m.value, s.value, sa.value
 
 
@@ -235,9 +269,18 @@ def threshold(s, sigma_mult):
 
 
 def children(uid, dim, split=2):
+    """The children's ids bits 0..63 (np.uint64); see children_w."""
+    return children_w(uid, dim, split)[0]
+
+
+def children_w(uid, dim, split=2):
+    """The children's ids as (bits 0..63 as np.uint64, bits 64..83 as
+    np.uint32)."""
     out = (C.c_uint64 * (split ** dim))()
-    lib().oracle_children(int(uid), dim, split, out)
-    return np.array(out[:], dtype=np.uint64)
+    out_hi = (C.c_uint32 * (split ** dim))()
+    a, b = _split_id(uid)
+    lib().oracle_children_w(a, b, dim, split, out, out_hi)
+    return np.array(out[:], dtype=np.uint64), np.array(out_hi[:], dtype=np.uint32)
 
 
 def validate(p: Problem) -> int:
@@ -247,7 +290,8 @@ def validate(p: Problem) -> int:
 @dataclass
 class Level:
     n: int
-    uid: np.ndarray
+    uid: np.ndarray      # id bits 0..63
+    uid_hi: np.ndarray   # id bits 64..83
     m: np.ndarray
     s: np.ndarray
     I: np.ndarray
@@ -277,21 +321,27 @@ class Run:
 
 def integrate(p: Problem, replay=None, band_eps: float = 0.0) -> Run:
     """Run the whole tree search.  ``replay``: list (per level) of (uids, sel)
-    from another run; decisions inside the ``band_eps`` margin are adopted."""
+    or (uids, sel, uids_hi) from another run; decisions inside the
+    ``band_eps`` margin are adopted."""
     L = lib()
     rp = None
     keep = []
     if replay is not None:
         rp = Replay()
         rp.n_levels = len(replay)
-        for l, (u, s) in enumerate(replay):
+        for l, item in enumerate(replay):
+            u, s = item[0], item[1]
+            uh = item[2] if len(item) > 2 and item[2] is not None else np.zeros(len(u), np.uint32)
             u = np.ascontiguousarray(u, dtype=np.uint64)
             s = np.ascontiguousarray(s, dtype=np.uint8)
-            order = np.argsort(u, kind="stable")
-            u, s = np.ascontiguousarray(u[order]), np.ascontiguousarray(s[order])
-            keep += [u, s]
+            uh = np.ascontiguousarray(uh, dtype=np.uint32)
+            order = np.lexsort((u, uh))  # by (uid_hi, uid)
+            u, s, uh = (np.ascontiguousarray(u[order]), np.ascontiguousarray(s[order]),
+                        np.ascontiguousarray(uh[order]))
+            keep += [u, s, uh]
             rp.n[l] = len(u)
             rp.uid[l] = u.ctypes.data_as(C.POINTER(C.c_uint64))
+            rp.uid_hi[l] = uh.ctypes.data_as(C.POINTER(C.c_uint32))
             rp.sel[l] = s.ctypes.data_as(C.POINTER(C.c_uint8))
     h = L.oracle_integrate(C.byref(p), C.byref(rp) if rp is not None else None, float(band_eps))
     if not h:
@@ -318,6 +368,7 @@ def integrate(p: Problem, replay=None, band_eps: float = 0.0) -> Run:
             run.levels.append(Level(
                 n=n,
                 uid=arr(L.oracle_level_uid, n, np.uint64),
+                uid_hi=arr(L.oracle_level_uid_hi, n, np.uint32),
                 m=arr(L.oracle_level_m, n, np.float64),
                 s=arr(L.oracle_level_s, n, np.float64),
                 I=arr(L.oracle_level_I, n * p.trials, np.float64).reshape(n, p.trials),

@@ -123,18 +123,38 @@ double oracle_uniform(uint32_t w)
     return (double)(2u * cell + 1u) * 0x1p-24;
 }
 
+/* Cube ids hold up to 84 bits: the low 64 in uid, bits 64..83 in uid_hi. */
+typedef unsigned __int128 or_u128;
+#define OR_ID_BITS 84
+
+static or_u128 wide_id(uint64_t lo, uint32_t hi) { return ((or_u128)hi << 64) | (or_u128)lo; }
+
+/* Counter word 1 of the stream of trial t of the cube (uid, level): bits 0..7
+ * the trial, 8..11 the level, 12..31 the id bits above 64 (zero for every id
+ * below 2^64, whose streams are therefore those of 64-bit ids). */
+static uint32_t ctr_word1(int trial, int level, uint32_t uid_hi)
+{
+    return (uint32_t)trial | ((uint32_t)level << 8) | (uid_hi << 12);
+}
+
 /* The RNG word that drives dimension i of sample s in trial t of the cube
  * (uid, level): word n = s*D + i of the stream keyed by the 64-bit seed, with
- * counter (n >> 2, t | level << 8, lo32(uid), hi32(uid)), lane n & 3. */
-uint32_t oracle_word(uint64_t seed, uint64_t uid, int level, int trial, int dim, int64_t s, int i)
+ * counter (n >> 2, t | level << 8 | uid_hi << 12, lo32(uid), hi32(uid)), lane
+ * n & 3. */
+uint32_t oracle_word_w(uint64_t seed, uint64_t uid, uint32_t uid_hi, int level, int trial, int dim, int64_t s,
+                       int i)
 {
     uint64_t n = (uint64_t)s * (uint64_t)dim + (uint64_t)i;
-    uint32_t ctr[4] = {(uint32_t)(n >> 2), (uint32_t)trial | ((uint32_t)level << 8),
-                       (uint32_t)uid, (uint32_t)(uid >> 32)};
+    uint32_t ctr[4] = {(uint32_t)(n >> 2), ctr_word1(trial, level, uid_hi), (uint32_t)uid, (uint32_t)(uid >> 32)};
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t out[4];
     oracle_philox4x32_10(ctr, key, out);
     return out[n & 3u];
+}
+
+uint32_t oracle_word(uint64_t seed, uint64_t uid, int level, int trial, int dim, int64_t s, int i)
+{
+    return oracle_word_w(seed, uid, 0, level, trial, dim, s, i);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -158,38 +178,46 @@ static uint64_t ipow_u64(uint64_t b, int e)
  * the path holding one base-b^D digit per split, and each digit c holding
  * the part along axis i as its base-b digit D-1-i (axis 0 most significant).
  * For b = 2 this is uid' = (uid << D) | c with bit D-1-i of c for axis i. */
-void oracle_cube_lattice(int dim, int divisions, int split, int level, uint64_t uid, uint64_t* K)
+void oracle_cube_lattice_w(int dim, int divisions, int split, int level, uint64_t uid_lo, uint32_t uid_hi,
+                           uint64_t* K)
 {
-    const uint64_t kids = ipow_u64((uint64_t)split, dim);
-    uint64_t path_scale = 1; /* (b^D)^level; overflows only when it reaches 2^64 */
+    const or_u128 uid = wide_id(uid_lo, uid_hi);
+    const or_u128 kids = (or_u128)ipow_u64((uint64_t)split, dim);
+    or_u128 path_scale = 1; /* (b^D)^level; saturates once it exceeds every id */
     int full = 0;
     for (int j = 0; j < level; ++j) {
-        if (path_scale > (~0ull) / kids) full = 1;
-        path_scale *= kids;
+        if (path_scale > ((or_u128)1 << OR_ID_BITS) / kids) full = 1;
+        else path_scale *= kids;
     }
-    /* the root index sits above the path digits (none left when they fill 64 bits) */
-    uint64_t root = full ? 0 : uid / path_scale;
+    /* the root index sits above the path digits (none left when they fill the id) */
+    or_u128 root = full ? 0 : uid / path_scale;
     for (int i = dim - 1; i >= 0; --i) {
-        K[i] = root % (uint64_t)divisions;
-        root /= (uint64_t)divisions;
+        K[i] = (uint64_t)(root % (or_u128)divisions);
+        root /= (or_u128)divisions;
     }
     for (int j = 1; j <= level; ++j) {
-        uint64_t c = uid;
+        or_u128 c = uid;
         for (int t = 0; t < level - j; ++t) c /= kids;
         c %= kids;
         for (int i = 0; i < dim; ++i) {
-            uint64_t digit = c;
-            for (int t = 0; t < dim - 1 - i; ++t) digit /= (uint64_t)split;
-            K[i] = (uint64_t)split * K[i] + digit % (uint64_t)split;
+            or_u128 digit = c;
+            for (int t = 0; t < dim - 1 - i; ++t) digit /= (or_u128)split;
+            K[i] = (uint64_t)split * K[i] + (uint64_t)(digit % (or_u128)split);
         }
     }
 }
 
+void oracle_cube_lattice(int dim, int divisions, int split, int level, uint64_t uid, uint64_t* K)
+{
+    oracle_cube_lattice_w(dim, divisions, split, level, uid, 0, K);
+}
+
 /* Lower corner, edge lengths and volume of the cube (uid, level). */
-void oracle_cube_bounds(const oracle_problem* p, int level, uint64_t uid, double* lo, double* h, double* vol)
+void oracle_cube_bounds_w(const oracle_problem* p, int level, uint64_t uid, uint32_t uid_hi, double* lo, double* h,
+                          double* vol)
 {
     uint64_t K[OR_MAX_DIM];
-    oracle_cube_lattice(p->dim, p->divisions, p->split, level, uid, K);
+    oracle_cube_lattice_w(p->dim, p->divisions, p->split, level, uid, uid_hi, K);
     const double parts = (double)ipow_u64((uint64_t)p->split, level); /* b^level, exact */
     double v = 1.0;
     for (int i = 0; i < p->dim; ++i) {
@@ -199,6 +227,11 @@ void oracle_cube_bounds(const oracle_problem* p, int level, uint64_t uid, double
         v = v * h[i];
     }
     *vol = v;
+}
+
+void oracle_cube_bounds(const oracle_problem* p, int level, uint64_t uid, double* lo, double* h, double* vol)
+{
+    oracle_cube_bounds_w(p, level, uid, 0, lo, h, vol);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -302,14 +335,20 @@ double oracle_f(int id, const double* prm, int dim, const double* x)
 }
 
 /* Sample point s of trial t in cube (uid, level): x_i = fma(h_i, u, lo_i). */
-void oracle_sample_x(const oracle_problem* p, int level, uint64_t uid, int trial, int64_t s, double* x)
+void oracle_sample_x_w(const oracle_problem* p, int level, uint64_t uid, uint32_t uid_hi, int trial, int64_t s,
+                       double* x)
 {
     double lo[OR_MAX_DIM], h[OR_MAX_DIM], vol;
-    oracle_cube_bounds(p, level, uid, lo, h, &vol);
+    oracle_cube_bounds_w(p, level, uid, uid_hi, lo, h, &vol);
     for (int i = 0; i < p->dim; ++i) {
-        double u = oracle_uniform(oracle_word(p->seed, uid, level, trial, p->dim, s, i));
+        double u = oracle_uniform(oracle_word_w(p->seed, uid, uid_hi, level, trial, p->dim, s, i));
         x[i] = fma(h[i], u, lo[i]);
     }
+}
+
+void oracle_sample_x(const oracle_problem* p, int level, uint64_t uid, int trial, int64_t s, double* x)
+{
+    oracle_sample_x_w(p, level, uid, 0, trial, s, x);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -319,12 +358,12 @@ void oracle_sample_x(const oracle_problem* p, int level, uint64_t uid, int trial
 /* f^2 and SA = sum |f| never feed a decision.  Returns 0, or OR_ENONFINITE   */
 /* if any f was not finite.                                                    */
 /* ------------------------------------------------------------------------- */
-int oracle_cube_trial(const oracle_problem* p, int level, uint64_t uid, int trial,
-                      double* I_t, double* S1_out, double* S2_out, double* SA_out)
+int oracle_cube_trial_w(const oracle_problem* p, int level, uint64_t uid, uint32_t uid_hi, int trial, double* I_t,
+                        double* S1_out, double* S2_out, double* SA_out)
 {
     const int D = p->dim;
     double lo[OR_MAX_DIM], h[OR_MAX_DIM], vol, x[OR_MAX_DIM];
-    oracle_cube_bounds(p, level, uid, lo, h, &vol);
+    oracle_cube_bounds_w(p, level, uid, uid_hi, lo, h, &vol);
     uint32_t key[2] = {(uint32_t)p->seed, (uint32_t)(p->seed >> 32)};
     uint32_t block[4];
     uint64_t cached = ~0ull;
@@ -335,8 +374,8 @@ int oracle_cube_trial(const oracle_problem* p, int level, uint64_t uid, int tria
             uint64_t n = (uint64_t)s * (uint64_t)D + (uint64_t)i;
             if ((n >> 2) != cached) { /* one Philox block serves four words */
                 cached = n >> 2;
-                uint32_t ctr[4] = {(uint32_t)cached, (uint32_t)trial | ((uint32_t)level << 8),
-                                   (uint32_t)uid, (uint32_t)(uid >> 32)};
+                uint32_t ctr[4] = {(uint32_t)cached, ctr_word1(trial, level, uid_hi), (uint32_t)uid,
+                                   (uint32_t)(uid >> 32)};
                 oracle_philox4x32_10(ctr, key, block);
             }
             double u = oracle_uniform(block[n & 3u]);
@@ -355,11 +394,17 @@ int oracle_cube_trial(const oracle_problem* p, int level, uint64_t uid, int tria
     return finite ? OR_OK : OR_ENONFINITE;
 }
 
+int oracle_cube_trial(const oracle_problem* p, int level, uint64_t uid, int trial, double* I_t, double* S1_out,
+                      double* S2_out, double* SA_out)
+{
+    return oracle_cube_trial_w(p, level, uid, 0, trial, I_t, S1_out, S2_out, SA_out);
+}
+
 /* Mean and standard deviation of the n1 trial values of one sub-domain
  * (Sec. 2.1).  Reading: population std (ddof = 0), two passes, serial sums.
  * I_out (length n1) may be NULL. */
-int oracle_cube(const oracle_problem* p, int level, uint64_t uid, double* I_out, double* m_out,
-                double* s_out, double* SA_out)
+int oracle_cube_w(const oracle_problem* p, int level, uint64_t uid, uint32_t uid_hi, double* I_out, double* m_out,
+                  double* s_out, double* SA_out)
 {
     const int n1 = p->trials;
     double I[256];
@@ -367,7 +412,7 @@ int oracle_cube(const oracle_problem* p, int level, uint64_t uid, double* I_out,
     int st = OR_OK;
     for (int t = 0; t < n1; ++t) {
         double sa;
-        if (oracle_cube_trial(p, level, uid, t, &I[t], NULL, NULL, &sa) != OR_OK) st = OR_ENONFINITE;
+        if (oracle_cube_trial_w(p, level, uid, uid_hi, t, &I[t], NULL, NULL, &sa) != OR_OK) st = OR_ENONFINITE;
         sa_tot += sa;
         if (I_out) I_out[t] = I[t];
     }
@@ -380,11 +425,17 @@ int oracle_cube(const oracle_problem* p, int level, uint64_t uid, double* I_out,
     *s_out = sqrt(ss / (double)n1);
     if (SA_out) {
         double lo[OR_MAX_DIM], h[OR_MAX_DIM], vol;
-        oracle_cube_bounds(p, level, uid, lo, h, &vol);
+        oracle_cube_bounds_w(p, level, uid, uid_hi, lo, h, &vol);
         *SA_out = vol * (sa_tot / ((double)p->samples * (double)n1));
     }
     if (!isfinite(*m_out) || !isfinite(*s_out)) st = OR_ENONFINITE;
     return st;
+}
+
+int oracle_cube(const oracle_problem* p, int level, uint64_t uid, double* I_out, double* m_out, double* s_out,
+                double* SA_out)
+{
+    return oracle_cube_w(p, level, uid, 0, I_out, m_out, s_out, SA_out);
 }
 
 /* Threshold over one level's standard deviations (Sec. 2.1: the threshold is
@@ -404,11 +455,20 @@ double oracle_threshold(const double* s, int64_t n, double sigma_mult, double* m
     return mu + sigma_mult * sd;
 }
 
-/* The b^D children of a cube, in order c = 0 .. b^D - 1. */
-void oracle_children(uint64_t uid, int dim, int split, uint64_t* out)
+/* The b^D children of a cube, in order c = 0 .. b^D - 1: uid * b^D + c. */
+void oracle_children_w(uint64_t uid, uint32_t uid_hi, int dim, int split, uint64_t* out, uint32_t* out_hi)
 {
     uint64_t nc = ipow_u64((uint64_t)split, dim);
-    for (uint64_t c = 0; c < nc; ++c) out[c] = uid * nc + c;
+    for (uint64_t c = 0; c < nc; ++c) {
+        or_u128 k = wide_id(uid, uid_hi) * (or_u128)nc + (or_u128)c;
+        out[c] = (uint64_t)k;
+        if (out_hi) out_hi[c] = (uint32_t)(k >> 64);
+    }
+}
+
+void oracle_children(uint64_t uid, int dim, int split, uint64_t* out)
+{
+    oracle_children_w(uid, 0, dim, split, out, NULL);
 }
 
 /* ------------------------------------------------------------------------- */
@@ -445,32 +505,24 @@ int oracle_validate(const oracle_problem* p)
     if (p->max_cubes_per_level < 1) return OR_EINVAL;
     for (int i = 0; i < p->dim; ++i)
         if (!isfinite(p->lower[i]) || !isfinite(p->upper[i]) || !(p->lower[i] < p->upper[i])) return OR_EINVAL;
-    /* uid must hold ceil(log2 d^D) root bits plus D bits per refinement */
-    int root_bits = 0;
+    /* every id below d^D * (b^D)^max_depth must fit OR_ID_BITS bits (for
+     * b = 2: the root bits plus D bits per refinement); d^D itself must fit
+     * 64 bits, and so must the lattice cells per axis, d * b^max_depth */
     {
-        /* bits needed for d^D - 1, computed exactly with overflow guard */
-        uint64_t k = 1;
+        const or_u128 lim = (or_u128)1 << OR_ID_BITS;
+        or_u128 top = 1, cells = (or_u128)p->divisions;
         for (int i = 0; i < p->dim; ++i) {
-            if (k > (~0ull) / (uint64_t)p->divisions) return OR_EINVAL;
-            k *= (uint64_t)p->divisions;
+            top *= (or_u128)p->divisions;
+            if (top > (or_u128)(~0ull)) return OR_EINVAL;
         }
-        uint64_t top = k - 1;
-        while (top) {
-            ++root_bits;
-            top >>= 1;
-        }
-    }
-    if (p->split == 2) {
-        if (root_bits + p->dim * p->max_depth > 64) return OR_EINVAL;
-    } else {
-        /* uid < d^D * (b^D)^max_depth must fit 64 bits */
-        uint64_t top = 1;
-        for (int i = 0; i < p->dim; ++i) top *= (uint64_t)p->divisions;
-        for (int l = 0; l < p->max_depth; ++l)
+        for (int l = 0; l < p->max_depth; ++l) {
             for (int i = 0; i < p->dim; ++i) {
-                if (top > (~0ull) / (uint64_t)p->split) return OR_EINVAL;
-                top *= (uint64_t)p->split;
+                top *= (or_u128)p->split;
+                if (top > lim) return OR_EINVAL;
             }
+            cells *= (or_u128)p->split;
+            if (cells > ((or_u128)1 << 64)) return OR_EINVAL;
+        }
     }
     return OR_OK;
 }
@@ -480,6 +532,7 @@ int oracle_validate(const oracle_problem* p)
 /*                                                                             */
 /* Readings of points the paper leaves open:                                   */
 /*  - level 0 holds the k = d^D root cubes; max_depth counts refinement rounds */
+/*    (cube ids hold up to 84 bits: see oracle_word_w);                       */
 /*    after it, so the paper's "partition depth" is max_depth + 1;             */
 /*  - a selected cube is split into 2^D children (every axis bisected; with  */
 /*    split = b, b^D children, b = d being the paper's k equal parts        */
@@ -504,7 +557,8 @@ int oracle_validate(const oracle_problem* p)
 /* ------------------------------------------------------------------------- */
 typedef struct {
     int64_t n;
-    uint64_t* uid;
+    uint64_t* uid;       /* id bits 0..63 */
+    uint32_t* uid_hi;    /* id bits 64..83 */
     double* m;
     double* s;
     double* I;      /* n * trials */
@@ -532,20 +586,26 @@ typedef struct {
 typedef struct {
     int32_t n_levels;
     int64_t n[OR_MAX_LEVELS];
-    const uint64_t* uid[OR_MAX_LEVELS]; /* ascending */
+    const uint64_t* uid[OR_MAX_LEVELS];    /* ascending by (uid_hi, uid) */
+    const uint32_t* uid_hi[OR_MAX_LEVELS]; /* NULL: all zero */
     const uint8_t* sel[OR_MAX_LEVELS];
 } oracle_replay;
 
-static int replay_lookup(const oracle_replay* rp, int level, uint64_t uid, int* decision)
+static or_u128 replay_id(const oracle_replay* rp, int level, int64_t i)
+{
+    return wide_id(rp->uid[level][i], rp->uid_hi[level] ? rp->uid_hi[level][i] : 0u);
+}
+
+static int replay_lookup(const oracle_replay* rp, int level, or_u128 uid, int* decision)
 {
     if (!rp || level >= rp->n_levels || !rp->uid[level]) return 0;
     int64_t a = 0, b = rp->n[level];
     while (a < b) {
         int64_t mid = a + (b - a) / 2;
-        if (rp->uid[level][mid] < uid) a = mid + 1;
+        if (replay_id(rp, level, mid) < uid) a = mid + 1;
         else b = mid;
     }
-    if (a < rp->n[level] && rp->uid[level][a] == uid) {
+    if (a < rp->n[level] && replay_id(rp, level, a) == uid) {
         *decision = rp->sel[level][a] ? 1 : 0;
         return 1;
     }
@@ -557,6 +617,7 @@ void oracle_free(oracle_run* r)
     if (!r) return;
     for (int l = 0; l < OR_MAX_LEVELS; ++l) {
         free(r->level[l].uid);
+        free(r->level[l].uid_hi);
         free(r->level[l].m);
         free(r->level[l].s);
         free(r->level[l].I);
@@ -584,7 +645,8 @@ oracle_run* oracle_integrate(const oracle_problem* p, const oracle_replay* rp, d
     /* level 0: every root cube, ascending */
     int64_t n = (int64_t)k;
     uint64_t* list = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n);
-    if (!list) { r->status = OR_ENOMEM; return r; }
+    uint32_t* list_hi = (uint32_t*)calloc((size_t)n, sizeof(uint32_t));
+    if (!list || !list_hi) { free(list); free(list_hi); r->status = OR_ENOMEM; return r; }
     for (int64_t c = 0; c < n; ++c) list[c] = (uint64_t)c;
 
     double sumM = 0.0, sumS2 = 0.0, sumA = 0.0;
@@ -592,6 +654,7 @@ oracle_run* oracle_integrate(const oracle_problem* p, const oracle_replay* rp, d
         oracle_level* L = &r->level[level];
         L->n = n;
         L->uid = list;
+        L->uid_hi = list_hi;
         L->m = (double*)malloc(sizeof(double) * (size_t)n);
         L->s = (double*)malloc(sizeof(double) * (size_t)n);
         L->I = (double*)malloc(sizeof(double) * (size_t)n * (size_t)n1);
@@ -602,7 +665,7 @@ oracle_run* oracle_integrate(const oracle_problem* p, const oracle_replay* rp, d
 
         /* direct MC with n1 trials in every sub-domain of the list */
         for (int64_t c = 0; c < n; ++c) {
-            if (oracle_cube(p, level, list[c], &L->I[c * n1], &L->m[c], &L->s[c], &L->sa[c]) != OR_OK)
+            if (oracle_cube_w(p, level, list[c], list_hi[c], &L->I[c * n1], &L->m[c], &L->s[c], &L->sa[c]) != OR_OK)
                 r->status = OR_ENONFINITE;
         }
         r->n_samples += (uint64_t)n * (uint64_t)n1 * (uint64_t)p->samples;
@@ -626,7 +689,7 @@ oracle_run* oracle_integrate(const oracle_problem* p, const oracle_replay* rp, d
                     if (margin <= band_eps) {
                         int dec;
                         L->n_in_band++;
-                        if (replay_lookup(rp, level, list[c], &dec)) {
+                        if (replay_lookup(rp, level, wide_id(list[c], list_hi[c]), &dec)) {
                             if (dec != sel) L->n_replayed++;
                             sel = dec;
                         }
@@ -683,14 +746,16 @@ oracle_run* oracle_integrate(const oracle_problem* p, const oracle_replay* rp, d
 
         /* split the selected cubes: children in parent order, c ascending */
         uint64_t* next = (uint64_t*)malloc(sizeof(uint64_t) * (size_t)n_next);
-        if (!next) { r->status = OR_ENOMEM; return r; }
+        uint32_t* next_hi = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n_next);
+        if (!next || !next_hi) { free(next); free(next_hi); r->status = OR_ENOMEM; return r; }
         int64_t w = 0;
         for (int64_t c = 0; c < n; ++c)
             if (L->sel[c]) {
-                oracle_children(list[c], D, p->split, &next[w]);
+                oracle_children_w(list[c], list_hi[c], D, p->split, &next[w], &next_hi[w]);
                 w += (int64_t)kids;
             }
         list = next;
+        list_hi = next_hi;
         n = (int64_t)n_next;
     }
     r->integral = sumM;
@@ -716,6 +781,7 @@ void oracle_run_totals(const oracle_run* r, double* out4, uint64_t* counts2)
 }
 int64_t oracle_level_n(const oracle_run* r, int l) { return r->level[l].n; }
 const uint64_t* oracle_level_uid(const oracle_run* r, int l) { return r->level[l].uid; }
+const uint32_t* oracle_level_uid_hi(const oracle_run* r, int l) { return r->level[l].uid_hi; }
 const double* oracle_level_m(const oracle_run* r, int l) { return r->level[l].m; }
 const double* oracle_level_s(const oracle_run* r, int l) { return r->level[l].s; }
 const double* oracle_level_I(const oracle_run* r, int l) { return r->level[l].I; }

@@ -315,10 +315,11 @@ class Integrator:
         tr.capacity = capacity
         bufs = []
         for l in range(min(req.max_depth + 1, _abi.MAX_LEVELS)):
-            b = dict(uid=np.zeros(capacity, np.uint64), m=np.zeros(capacity), s=np.zeros(capacity),
-                     sel=np.zeros(capacity, np.uint8), S1=np.zeros(capacity * req.trials),
+            b = dict(uid=np.zeros(capacity, np.uint64), uid_hi=np.zeros(capacity, np.uint32), m=np.zeros(capacity),
+                     s=np.zeros(capacity), sel=np.zeros(capacity, np.uint8), S1=np.zeros(capacity * req.trials),
                      S2=np.zeros(capacity * req.trials))
             tr.uid[l] = b["uid"].ctypes.data_as(C.POINTER(C.c_uint64))
+            tr.uid_hi[l] = b["uid_hi"].ctypes.data_as(C.POINTER(C.c_uint32))
             tr.m[l] = b["m"].ctypes.data_as(C.POINTER(C.c_double))
             tr.s[l] = b["s"].ctypes.data_as(C.POINTER(C.c_double))
             tr.sel[l] = b["sel"].ctypes.data_as(C.POINTER(C.c_uint8))
@@ -334,7 +335,8 @@ class Integrator:
             n = int(tr.n[l])
             c = min(n, len(bufs[l]["uid"]))
             b = bufs[l]
-            out.append(dict(n=n, uid=b["uid"][:c].copy(), m=b["m"][:c].copy(), s=b["s"][:c].copy(),
+            out.append(dict(n=n, uid=b["uid"][:c].copy(), uid_hi=b["uid_hi"][:c].copy(), m=b["m"][:c].copy(),
+                            s=b["s"][:c].copy(),
                             sel=b["sel"][:c].copy(), S1=b["S1"][:c * req.trials].reshape(c, req.trials).copy(),
                             S2=b["S2"][:c * req.trials].reshape(c, req.trials).copy()))
         return out

@@ -70,6 +70,7 @@ class Trace(C.Structure):
         ("uid", C.POINTER(C.c_uint64) * MAX_LEVELS), ("m", C.POINTER(C.c_double) * MAX_LEVELS),
         ("s", C.POINTER(C.c_double) * MAX_LEVELS), ("sel", C.POINTER(C.c_uint8) * MAX_LEVELS),
         ("S1", C.POINTER(C.c_double) * MAX_LEVELS), ("S2", C.POINTER(C.c_double) * MAX_LEVELS),
+        ("uid_hi", C.POINTER(C.c_uint32) * MAX_LEVELS),
     ]
 
 

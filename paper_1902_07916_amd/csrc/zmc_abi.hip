@@ -172,18 +172,19 @@ int validate(const zmc_request& r)
     bool ovf = false;
     const uint64_t k = ipow_sat((uint64_t)r.divisions_per_axis, r.dim, &ovf);
     if (ovf) return fail(ZMC_EINVAL, "d^D overflows 64 bits");
-    int root_bits = 0;
-    for (uint64_t t = k - 1; t; t >>= 1) ++root_bits;
-    if (b == 2) {
-        if (root_bits + r.dim * r.max_depth > 64) return fail(ZMC_EINVAL, "uid would overflow 64 bits");
-    } else {
-        // uid < d^D * (b^D)^max_depth
-        uint64_t top = k;
-        for (int l = 0; l < r.max_depth; ++l)
+    {
+        // every cube id is below d^D * (b^D)^max_depth, which must fit the
+        // 84 id bits; the lattice cells per axis, d * b^max_depth, 64 bits
+        const unsigned __int128 lim = (unsigned __int128)1 << kIdBits;
+        unsigned __int128 top = k, cells = (unsigned __int128)r.divisions_per_axis;
+        for (int l = 0; l < r.max_depth; ++l) {
             for (int i = 0; i < r.dim; ++i) {
-                if (top > UINT64_MAX / b) return fail(ZMC_EINVAL, "uid would overflow 64 bits");
                 top *= b;
+                if (top > lim) return fail(ZMC_EINVAL, "cube ids would overflow 84 bits");
             }
+            cells *= b;
+            if (cells > ((unsigned __int128)1 << 64)) return fail(ZMC_EINVAL, "lattice cells per axis overflow 64 bits");
+        }
     }
     const int64_t cap = r.max_cubes_per_level > 0 ? r.max_cubes_per_level : ZMC_DEFAULT_MAX_CUBES;
     if (k > (uint64_t)cap) return fail(ZMC_EINVAL, "d^D exceeds max_cubes_per_level");

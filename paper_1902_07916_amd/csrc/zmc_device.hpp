@@ -87,6 +87,7 @@ struct SampleArgs {
     int64_t unit0;       // first unit of this launch (units are numbered over the level's bucket)
     int64_t total_units; // units of this launch
     const uint64_t* uid;
+    const uint32_t* uid_hi; // id bits 64..83 per cube; NULL when every id of the level is below 2^64
     double2* partial;
     int32_t* seg_flags;  // per segment of the level (0 at the level's start):
                          // kRangeLost when an FP32 unit's sum fell below
@@ -107,6 +108,46 @@ struct alignas(16) SegStats {
     int32_t decision, nonfinite;
     int32_t range_lost, pad;
 };
+
+// ---------------------------------------------------------------------------
+// Cube ids of up to 84 bits: bits 0..63 (lo) and 64..83 (hi).  Bits 64..83
+// enter the RNG counter's word 1 above the trial and the level, so every id
+// below 2^64 keeps the stream of a 64-bit id.
+// ---------------------------------------------------------------------------
+constexpr int kIdBits = 84;
+
+__device__ __forceinline__ uint32_t ctr_word1(int trial, int level, uint32_t uid_hi)
+{
+    return (uint32_t)trial | ((uint32_t)level << 8) | (uid_hi << 12);
+}
+
+// Bits 0..63 of (hi:lo) >> k.
+__device__ __forceinline__ uint64_t shr_id(uint64_t lo, uint32_t hi, int k)
+{
+    if (k >= kIdBits) return 0;
+    if (k >= 64) return (uint64_t)hi >> (k - 64);
+    if (k == 0) return lo;
+    return (lo >> k) | ((uint64_t)hi << (64 - k));
+}
+
+// (hi:lo) /= k in place for 1 <= k < 2^32, returning the remainder: long
+// division over 32-bit limbs with 64-bit intermediates.
+__device__ __forceinline__ uint64_t divmod_id(uint64_t& lo, uint32_t& hi, uint64_t k)
+{
+    uint64_t r = 0;
+    const uint64_t t2 = hi;
+    const uint64_t q2 = t2 / k;
+    r = t2 - q2 * k;
+    const uint64_t t1 = (r << 32) | (lo >> 32);
+    const uint64_t q1 = t1 / k;
+    r = t1 - q1 * k;
+    const uint64_t t0 = (r << 32) | (lo & 0xffffffffull);
+    const uint64_t q0 = t0 / k;
+    r = t0 - q0 * k;
+    hi = (uint32_t)q2;
+    lo = (q1 << 32) | q0;
+    return r;
+}
 
 // ---------------------------------------------------------------------------
 // Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64 products

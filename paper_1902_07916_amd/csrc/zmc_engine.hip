@@ -73,6 +73,18 @@ int split_of(const zmc_request& r) { return r.split ? r.split : 2; }
 int64_t kids_of(const zmc_request& r) { return (int64_t)ipow_u64((uint64_t)split_of(r), r.dim); }
 } // namespace
 
+// Whether a request's cube ids can reach 2^64 (d^D * (split^D)^max_depth >
+// 2^64): its levels then carry id bits 64..83 in a second array.
+bool wide_ids(const zmc_request& r)
+{
+    unsigned __int128 top = 1;
+    for (int i = 0; i < r.dim; ++i) top *= (unsigned __int128)r.divisions_per_axis;
+    const unsigned __int128 lim = (unsigned __int128)1 << 64;
+    for (int l = 0; l < r.max_depth && top <= lim; ++l)
+        for (int i = 0; i < r.dim && top <= lim; ++i) top *= (unsigned __int128)split_of(r);
+    return top > lim;
+}
+
 void set_error(const std::string& s) { g_err = s; }
 const char* last_error() { return g_err.c_str(); }
 
@@ -292,9 +304,10 @@ size_t request_bytes(const zmc_request& r, const TileTable& t)
     const int64_t kids = kids_of(r);
     const int64_t per_group_thr = r.threshold_scope == 1 ? (8 + kids - 1) / kids : 0;
     const int64_t per_tile = (int64_t)sizeof(TileRec);
-    const int64_t per_cube = 8 + 16LL * r.trials * chunks_for(r, t) + 8 + 8 + 1 + per_group_thr;
+    const int64_t id_bytes = wide_ids(r) ? 8 + 4 : 8; // ids above 2^64 take a second array
+    const int64_t per_cube = id_bytes + 16LL * r.trials * chunks_for(r, t) + 8 + 8 + 1 + per_group_thr;
     const int64_t tiles = ceil_div(worst, kTileCubes) + 1;
-    return (size_t)(worst * per_cube + tiles * per_tile + worst_next * 8 + 8 * 256 + 4 * 4096);
+    return (size_t)(worst * per_cube + tiles * per_tile + worst_next * id_bytes + 10 * 256 + 4 * 4096);
 }
 
 void Engine::record_level(HostSlot& hs, const SegStats& S, int64_t n, double ms, float sample_ms, int launches)
@@ -461,6 +474,7 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
         a.bsegs = d_bsegs_ + L.off;
         a.n_bsegs = L.count;
         a.uid = cur_uid;
+        a.uid_hi = cur_hi_;
         a.partial = partial;
         a.seg_flags = d_flags;
         // one launch, or launches of at most chunk_samples_ samples each
@@ -491,6 +505,7 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
     la.n_segs = ns;
     la.n_tiles = tile;
     la.uid = cur_uid;
+    la.uid_hi = cur_hi_;
     la.partial = partial;
     la.m = cur_m_;
     la.s = cur_s_;
@@ -505,13 +520,19 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
     la.seg_count = d_seg_count_;
     la.host_stats = stats_only ? nullptr : d_hstats_;
     la.seg_flags = d_flags;
-    // small levels fold the per-segment steps into the tile kernels
+    // small levels fold the per-segment steps into the tile kernels; a
+    // level of one-tile segments without per-parent thresholds runs them all
+    // in one launch
     la.fused = tile <= kFuseMaxTiles ? 1 : 0;
-    ZMC_HIP(launch_finalize(la, st));
-    if (!stats_only) {
-        if (any_thr) ZMC_HIP(launch_threshold(la, st));
-        if (groups) ZMC_HIP(launch_group_threshold(la, st));
-        ZMC_HIP(launch_select(la, st));
+    if (!stats_only && tile == ns && groups == 0) {
+        ZMC_HIP(launch_level_small(la, st));
+    } else {
+        ZMC_HIP(launch_finalize(la, st));
+        if (!stats_only) {
+            if (any_thr) ZMC_HIP(launch_threshold(la, st));
+            if (groups) ZMC_HIP(launch_group_threshold(la, st));
+            ZMC_HIP(launch_select(la, st));
+        }
     }
     if (trace && ns == 1) {
         const HostSlot& hs = slots_[live[0].slot];
@@ -522,6 +543,12 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
             const int n1 = hs.req.trials;
             if (c > 0) {
                 if (trace->uid[l]) ZMC_HIP(hipMemcpyAsync(trace->uid[l], cur_uid, c * 8, hipMemcpyDeviceToHost, st));
+                if (trace->uid_hi[l]) {
+                    if (cur_hi_)
+                        ZMC_HIP(hipMemcpyAsync(trace->uid_hi[l], cur_hi_, c * 4, hipMemcpyDeviceToHost, st));
+                    else
+                        memset(trace->uid_hi[l], 0, (size_t)c * 4);
+                }
                 if (trace->m[l]) ZMC_HIP(hipMemcpyAsync(trace->m[l], cur_m_, c * 8, hipMemcpyDeviceToHost, st));
                 if (trace->s[l]) ZMC_HIP(hipMemcpyAsync(trace->s[l], cur_s_, c * 8, hipMemcpyDeviceToHost, st));
                 if (trace->sel[l]) ZMC_HIP(hipMemcpyAsync(trace->sel[l], cur_sel_, c, hipMemcpyDeviceToHost, st));
@@ -576,9 +603,13 @@ int Engine::next_list(hipStream_t st, std::vector<LiveSeg>& live, const std::vec
     (void)root_base;
     const int other = cur_side ^ 1;
     uint64_t* next_uid = nullptr;
+    uint32_t* next_hi = nullptr;
+    bool wide = false;
+    for (const LiveSeg& g : nxt) wide |= slots_[g.slot].wide;
     if (total > 0) {
         next_uid = (uint64_t*)arena_.alloc(other, (size_t)total * sizeof(uint64_t));
-        if (!next_uid) {
+        if (wide) next_hi = (uint32_t*)arena_.alloc(other, (size_t)total * sizeof(uint32_t));
+        if (!next_uid || (wide && !next_hi)) {
             set_error("arena exhausted (next level list)");
             return ZMC_ENOMEM;
         }
@@ -592,9 +623,11 @@ int Engine::next_list(hipStream_t st, std::vector<LiveSeg>& live, const std::vec
         la.n_segs = ns;
         la.n_tiles = n_tiles_;
         la.uid = cur_uid;
+        la.uid_hi = cur_hi_;
         la.sel = cur_sel_;
         la.tiles = cur_tiles_;
         la.next_uid = next_uid;
+        la.next_uid_hi = next_hi;
         ZMC_HIP(launch_spawn(la, st));
     }
     if (!fresh.empty()) {
@@ -607,6 +640,7 @@ int Engine::next_list(hipStream_t st, std::vector<LiveSeg>& live, const std::vec
         for (auto& f : fresh) mx = std::max(mx, f.n_cubes);
         ra.blocks_per_seg = (int)std::min<int64_t>(64, ceil_div(mx, 4096));
         ra.uid = next_uid;
+        ra.uid_hi = next_hi;
         ZMC_HIP(launch_roots(ra, st));
     }
     // levels advance for the split segments
@@ -616,6 +650,7 @@ int Engine::next_list(hipStream_t st, std::vector<LiveSeg>& live, const std::vec
     arena_.reset(cur_side);
     cur_side = other;
     cur_uid = next_uid;
+    cur_hi_ = next_hi;
     live.swap(nxt);
     return ZMC_OK;
 }
@@ -629,6 +664,7 @@ int Engine::drive(hipStream_t st, Admission& adm, zmc_trace* trace, const std::a
     for (int i = max_slots_ - 1; i >= 0; --i) free_ids.push_back(i);
     std::vector<LiveSeg> live;
     uint64_t* cur_uid = nullptr;
+    cur_hi_ = nullptr;
     int cur_side = 0;
     arena_.reset(0);
     arena_.reset(1);
@@ -671,6 +707,7 @@ int Engine::drive(hipStream_t st, Admission& adm, zmc_trace* trace, const std::a
                 live.clear();
                 split.clear();
                 cur_uid = nullptr;
+                cur_hi_ = nullptr;
                 arena_.reset(0);
                 arena_.reset(1);
                 if (rc == ZMC_EDEVICE) return rc;
@@ -707,6 +744,7 @@ int Engine::drive(hipStream_t st, Admission& adm, zmc_trace* trace, const std::a
             free_ids.pop_back();
             slots_[id] = in;
             HostSlot& hs = slots_[id];
+            hs.wide = wide_ids(hs.req);
             hs.level = 0;
             hs.totM = hs.totS2 = 0.0;
             reserved += hs.reserve;
@@ -742,6 +780,7 @@ int Engine::drive(hipStream_t st, Admission& adm, zmc_trace* trace, const std::a
             }
             live.clear();
             cur_uid = nullptr;
+            cur_hi_ = nullptr;
             arena_.reset(0);
             arena_.reset(1);
             continue;
@@ -807,6 +846,7 @@ int Engine::cube_estimates(const zmc_request& req, int level, const uint64_t* ui
     if (rc != ZMC_OK) return rc;
     uint64_t* d_uid = (uint64_t*)arena_.alloc(1, (size_t)n * 8);
     if (!d_uid) return ZMC_ENOMEM;
+    cur_hi_ = nullptr; // ids given here are below 2^64
     ZMC_HIP(hipMemcpyAsync(d_uid, uids, (size_t)n * 8, hipMemcpyHostToDevice, st));
     std::vector<LiveSeg> live{{0, n}};
     rc = step(st, live, d_uid, 0, nullptr, true, S1 != nullptr || S2 != nullptr);

@@ -104,6 +104,7 @@ struct HostSlot {
     double totM = 0.0, totS2 = 0.0;
     uint64_t ticket = 0;
     size_t reserve = 0;  // serving: worst-case bytes held for it
+    bool wide = false;   // its cube ids can reach 2^64 (see wide_ids)
     bool cancel = false;
     std::chrono::steady_clock::time_point t_submit;
 };
@@ -121,6 +122,7 @@ int groups_for(const zmc_request& r, const TileTable& t);
 int chunks_for(const zmc_request& r, const TileTable& t);
 // Worst-case device bytes of one request's tree (see Engine::reservation_bytes).
 size_t request_bytes(const zmc_request& r, const TileTable& t);
+bool wide_ids(const zmc_request& r);
 
 class Engine {
 public:
@@ -206,6 +208,7 @@ private:
     int64_t chunk_samples_ = 0;
     // arrays of the level last stepped (valid until its spawn is enqueued)
     uint64_t* cur_uid_ = nullptr;
+    uint32_t* cur_hi_ = nullptr; // id bits 64..83 of the current list, or NULL
     double* cur_m_ = nullptr;
     double* cur_s_ = nullptr;
     uint8_t* cur_sel_ = nullptr;

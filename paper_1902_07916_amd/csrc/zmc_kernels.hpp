@@ -12,6 +12,8 @@
 //   seg_decide  per integral: totals, stop rules, rank base of every tile
 //   spawn       2^D children of every split cube, in list order
 //   roots       level-0 list of a newly admitted integral
+//   level_small finalize .. seg_decide in one launch when every segment of
+//               the level is a single tile
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -27,6 +29,7 @@ struct LevelArgs {
     int32_t fused;           // per-segment steps in the tile kernels' last blocks
     int64_t n_tiles;
     const uint64_t* uid;
+    const uint32_t* uid_hi;  // id bits 64..83, or NULL (all zero)
     const double2* partial;
     double* m;
     double* s;
@@ -37,6 +40,7 @@ struct LevelArgs {
     double* tr_S1;           // optional per (cube, trial) sums (trace)
     double* tr_S2;
     uint64_t* next_uid;      // spawn output
+    uint32_t* next_uid_hi;   // spawn output: id bits 64..83, or NULL
     double* gthr;            // per-parent thresholds, one per sibling group
     int64_t n_groups;
     int32_t* seg_count;      // per segment: tile blocks done (0 between kernels)
@@ -49,6 +53,7 @@ struct RootArgs {
     int32_t n_segs;
     int32_t blocks_per_seg;
     uint64_t* uid;
+    uint32_t* uid_hi; // written 0 when not NULL
 };
 
 // Launchers; each returns the hipError_t of its launch.
@@ -68,6 +73,9 @@ hipError_t launch_sample(int integrand, int dim, int eval, int hint, int grid, i
                          const SampleArgs& a);
 const void* sample_kernel_ptr(int integrand, int dim, int eval, int hint);
 hipError_t launch_finalize(const LevelArgs& a, hipStream_t st);
+// finalize + threshold + selection + decision of a level whose segments are
+// all one tile without per-parent thresholds, one block per segment
+hipError_t launch_level_small(const LevelArgs& a, hipStream_t st);
 hipError_t launch_threshold(const LevelArgs& a, hipStream_t st);
 hipError_t launch_group_threshold(const LevelArgs& a, hipStream_t st);
 hipError_t launch_select(const LevelArgs& a, hipStream_t st);

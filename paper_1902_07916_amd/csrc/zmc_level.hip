@@ -218,12 +218,10 @@ __device__ void seg_decide(const LevelArgs& a, int si);
 // there.  Larger rows (many trials or chunks) are read from memory directly.
 constexpr int kStage = 2560; // 40 KiB of (S1, S2) pairs
 
-__global__ __launch_bounds__(kLevelThreads) void finalize_kernel(const LevelArgs a)
+__device__ void finalize_tile(const LevelArgs& a, int64_t tile, int si)
 {
     __shared__ double sh[kWaves];
     __shared__ double2 stage[kStage];
-    const int64_t tile = blockIdx.x;
-    const int si = seg_of_tile(a.segs, a.n_segs, tile);
     const Segment& sg = a.segs[si];
     const SlotDesc& sd = a.slots[sg.slot];
     const int D = sd.dim, n1 = sd.trials, nch = sd.nch;
@@ -285,18 +283,23 @@ __global__ __launch_bounds__(kLevelThreads) void finalize_kernel(const LevelArgs
         a.tiles[tile].sum_s = tot;
         a.tiles[tile].nonfinite = any_bad;
     }
+}
+
+__global__ __launch_bounds__(kLevelThreads) void finalize_kernel(const LevelArgs a)
+{
+    const int64_t tile = blockIdx.x;
+    const int si = seg_of_tile(a.segs, a.n_segs, tile);
+    const Segment& sg = a.segs[si];
+    finalize_tile(a, tile, si);
     if (a.fused && sg.need_thr && !sg.group_size && last_tile_of_segment(a.seg_count, si, sg.n_tiles))
         seg_mean(a, si);
 }
 
 // ---- threshold: std of s around the mean, per segment ----------------------
-__global__ __launch_bounds__(kLevelThreads) void tile_sqdev_kernel(const LevelArgs a)
+__device__ void sqdev_tile(const LevelArgs& a, int64_t tile, int si)
 {
     __shared__ double sh[kWaves];
-    const int64_t tile = blockIdx.x;
-    const int si = seg_of_tile(a.segs, a.n_segs, tile);
     const Segment& sg = a.segs[si];
-    if (!sg.need_thr || sg.group_size) return;
     const double mu = a.stats[si].mu;
     const int64_t first = (tile - sg.tile_base) * kTileCubes;
     double acc = 0.0;
@@ -308,6 +311,15 @@ __global__ __launch_bounds__(kLevelThreads) void tile_sqdev_kernel(const LevelAr
     }
     const double tot = block_sum(acc, sh);
     if (threadIdx.x == 0) a.tiles[tile].sum_sq = tot;
+}
+
+__global__ __launch_bounds__(kLevelThreads) void tile_sqdev_kernel(const LevelArgs a)
+{
+    const int64_t tile = blockIdx.x;
+    const int si = seg_of_tile(a.segs, a.n_segs, tile);
+    const Segment& sg = a.segs[si];
+    if (!sg.need_thr || sg.group_size) return;
+    sqdev_tile(a, tile, si);
     if (a.fused && last_tile_of_segment(a.seg_count, si, sg.n_tiles)) seg_thr(a, si);
 }
 
@@ -364,10 +376,8 @@ __global__ __launch_bounds__(kLevelThreads) void group_thr_kernel(const LevelArg
 }
 
 // ---- selection: split = s > thr; accepted and selected sums per tile -------
-__global__ __launch_bounds__(kLevelThreads) void tile_select_kernel(const LevelArgs a)
+__device__ void select_tile(const LevelArgs& a, int64_t tile, int si)
 {
-    const int64_t tile = blockIdx.x;
-    const int si = seg_of_tile(a.segs, a.n_segs, tile);
     const Segment& sg = a.segs[si];
     const bool thr_on = sg.need_thr != 0;
     const double level_thr = (thr_on && !sg.group_size) ? a.stats[si].thr : 0.0;
@@ -402,6 +412,14 @@ __global__ __launch_bounds__(kLevelThreads) void tile_select_kernel(const LevelA
         T.min_margin = tot.margin;
         T.n_sel = tot.nsel;
     }
+}
+
+__global__ __launch_bounds__(kLevelThreads) void tile_select_kernel(const LevelArgs a)
+{
+    const int64_t tile = blockIdx.x;
+    const int si = seg_of_tile(a.segs, a.n_segs, tile);
+    const Segment& sg = a.segs[si];
+    select_tile(a, tile, si);
     if (a.fused && last_tile_of_segment(a.seg_count, si, sg.n_tiles)) seg_decide(a, si);
 }
 
@@ -505,10 +523,39 @@ __device__ void seg_decide(const LevelArgs& a, int si)
 
 __global__ __launch_bounds__(kLevelThreads) void seg_decide_kernel(const LevelArgs a) { seg_decide(a, blockIdx.x); }
 
+// ---- a whole small level in one launch ----------------------------------------
+// When every segment of the level is one tile (at most 1024 cubes) and no
+// segment forms per-parent thresholds, one block per segment runs finalize,
+// the mean of s, the threshold and the decision in sequence.  With one tile
+// per segment each per-segment reduction of the multi-launch path reduces a
+// single tile record, so this is the same arithmetic in the same order and
+// the results are bitwise those of the three launches.
+__global__ __launch_bounds__(kLevelThreads) void level_small_kernel(const LevelArgs a)
+{
+    const int si = blockIdx.x;
+    const Segment& sg = a.segs[si];
+    const int64_t tile = sg.tile_base;
+    const bool thr = sg.need_thr && !sg.group_size;
+    finalize_tile(a, tile, si);
+    __syncthreads();
+    if (thr) {
+        seg_mean(a, si);
+        __syncthreads();
+        sqdev_tile(a, tile, si);
+        __syncthreads();
+        seg_thr(a, si);
+        __syncthreads();
+    }
+    select_tile(a, tile, si);
+    __syncthreads();
+    seg_decide(a, si);
+}
+
 // ---- spawn: children of the selected cubes, in list order ------------------
 __global__ __launch_bounds__(kLevelThreads) void spawn_kernel(const LevelArgs a)
 {
     __shared__ uint64_t list[kTileCubes];
+    __shared__ uint32_t list_hi[kTileCubes];
     __shared__ int shf[kWaves];
     const int64_t tile = blockIdx.x;
     const int si = seg_of_tile(a.segs, a.n_segs, tile);
@@ -524,22 +571,34 @@ __global__ __launch_bounds__(kLevelThreads) void spawn_kernel(const LevelArgs a)
         const int flag = (cl < sg.n_cubes) ? a.sel[sg.cube_base + cl] : 0;
         int total;
         const int pos = block_excl_scan_flag(flag, shf, &total);
-        if (flag) list[base + pos] = a.uid[sg.cube_base + cl];
+        if (flag) {
+            list[base + pos] = a.uid[sg.cube_base + cl];
+            list_hi[base + pos] = a.uid_hi ? a.uid_hi[sg.cube_base + cl] : 0u;
+        }
         base += total;
     }
     __syncthreads();
     const int64_t n_writes = (int64_t)base * kids;
-    uint64_t* out = a.next_uid + sg.child_base + a.tiles[tile].sel_prefix * kids;
+    const int64_t first_out = sg.child_base + a.tiles[tile].sel_prefix * kids;
+    uint64_t* out = a.next_uid + first_out;
+    uint32_t* out_hi = a.next_uid_hi ? a.next_uid_hi + first_out : nullptr;
+    // child c of (hi:lo) is (hi:lo) * kids + c; with bisection (hi:lo) << D | c
     if (sd.split == 2) {
         const uint64_t mask = (1ull << D) - 1ull;
         for (int64_t w = threadIdx.x; w < n_writes; w += kLevelThreads) {
             const uint64_t parent = list[w >> D];
             out[w] = (parent << D) | ((uint64_t)w & mask);
+            if (out_hi) out_hi[w] = (list_hi[w >> D] << D) | (uint32_t)(parent >> (64 - D));
         }
     } else {
         for (int64_t w = threadIdx.x; w < n_writes; w += kLevelThreads) {
             const int64_t i = w / kids;
-            out[w] = list[i] * (uint64_t)kids + (uint64_t)(w - i * kids);
+            const uint64_t plo = list[i] * (uint64_t)kids;
+            const uint64_t lo = plo + (uint64_t)(w - i * kids);
+            out[w] = lo;
+            if (out_hi)
+                out_hi[w] = (uint32_t)((uint64_t)list_hi[i] * (uint64_t)kids + __umul64hi(list[i], (uint64_t)kids) +
+                                       (lo < plo ? 1u : 0u));
         }
     }
 }
@@ -551,8 +610,10 @@ __global__ __launch_bounds__(kLevelThreads) void roots_kernel(const RootArgs a)
     const int part = blockIdx.x % a.blocks_per_seg;
     const Segment& sg = a.segs[si];
     for (int64_t r = (int64_t)part * kLevelThreads + threadIdx.x; r < sg.n_cubes;
-         r += (int64_t)a.blocks_per_seg * kLevelThreads)
+         r += (int64_t)a.blocks_per_seg * kLevelThreads) {
         a.uid[sg.cube_base + r] = (uint64_t)r;
+        if (a.uid_hi) a.uid_hi[sg.cube_base + r] = 0u;
+    }
 }
 
 // ---- debug entry points ------------------------------------------------------
@@ -579,7 +640,7 @@ __global__ void debug_points_kernel(const SlotDesc* sdp, int level, uint64_t uid
     const int64_t s = s0 + k;
     for (int i = 0; i < D; ++i) {
         const uint64_t nw = (uint64_t)s * (uint64_t)D + (uint64_t)i;
-        const U4 r = philox4x32_10((uint32_t)(nw >> 2), (uint32_t)trial | ((uint32_t)level << 8), (uint32_t)uid,
+        const U4 r = philox4x32_10((uint32_t)(nw >> 2), ctr_word1(trial, level, 0u), (uint32_t)uid,
                                    (uint32_t)(uid >> 32), (uint32_t)sd.seed, (uint32_t)(sd.seed >> 32));
         const uint32_t words[4] = {r.x, r.y, r.z, r.w};
         const uint32_t w = words[nw & 3u];
@@ -593,6 +654,13 @@ hipError_t launch_finalize(const LevelArgs& a, hipStream_t st)
 {
     if (a.n_tiles <= 0) return hipSuccess;
     hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)a.n_tiles), dim3(kLevelThreads), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_level_small(const LevelArgs& a, hipStream_t st)
+{
+    if (a.n_segs <= 0) return hipSuccess;
+    hipLaunchKernelGGL(level_small_kernel, dim3((unsigned)a.n_segs), dim3(kLevelThreads), 0, st, a);
     return hipGetLastError();
 }
 

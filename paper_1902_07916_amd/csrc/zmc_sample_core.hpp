@@ -37,12 +37,14 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 template <int D>
-__device__ __forceinline__ void corner(const SlotDesc& sd, int level, uint64_t uid, double* lo, double* h)
+__device__ __forceinline__ void corner(const SlotDesc& sd, int level, uint64_t uid, uint32_t uid_hi, double* lo,
+                                       double* h)
 {
     uint64_t K[D];
     const uint32_t d = (uint32_t)sd.divisions;
     if (sd.split == 2) {
-        uint64_t root = (D * level >= 64) ? 0 : (uid >> (uint64_t)(D * level));
+        // uid = root << (D * level) | path, D bits per split
+        uint64_t root = shr_id(uid, uid_hi, D * level);
         if (root < (1ull << 32)) {
             uint32_t r32 = (uint32_t)root;
 #pragma unroll
@@ -58,7 +60,7 @@ __device__ __forceinline__ void corner(const SlotDesc& sd, int level, uint64_t u
             }
         }
         for (int j = 1; j <= level; ++j) {
-            const uint64_t c = uid >> (uint64_t)(D * (level - j));
+            const uint64_t c = shr_id(uid, uid_hi, D * (level - j));
 #pragma unroll
             for (int i = 0; i < D; ++i) K[i] = 2u * K[i] + ((c >> (uint64_t)(D - 1 - i)) & 1u);
         }
@@ -68,30 +70,33 @@ __device__ __forceinline__ void corner(const SlotDesc& sd, int level, uint64_t u
             lo[i] = fma((double)K[i], h[i], sd.lower[i]);
         }
     } else {
-        // b-way splits: base-b^D path digits (per unit, so plain divisions)
+        // b-way splits: uid = root * kids^level + path, one base-kids digit
+        // per split (kids = b^D <= 2^24).  The digits come off the low end,
+        // the last split's first, and each adds its base-b digit for axis i
+        // at the place value b^(splits after it): K_i = root_i b^level +
+        // sum over splits j of digit_{j,i} b^(level - j).
         const uint64_t b = (uint64_t)sd.split, kids = (uint64_t)sd.kids;
-        uint64_t root = uid;
-        for (int j = 0; j < level; ++j) root /= kids;
+        uint64_t rest = uid;
+        uint32_t rest_hi = uid_hi;
+        uint64_t mult = 1;
 #pragma unroll
-        for (int i = D - 1; i >= 0; --i) {
-            K[i] = root % d;
-            root /= d;
-        }
-        uint64_t parts = 1;
-        for (int j = 1; j <= level; ++j) {
-            uint64_t c = uid;
-            for (int t = 0; t < level - j; ++t) c /= kids;
-            c %= kids;
-            uint64_t digit[D];
+        for (int i = 0; i < D; ++i) K[i] = 0;
+        for (int j = 0; j < level; ++j) {
+            uint64_t c = divmod_id(rest, rest_hi, kids);
 #pragma unroll
             for (int i = D - 1; i >= 0; --i) {
-                digit[i] = c % b;
+                K[i] += (c % b) * mult;
                 c /= b;
             }
-#pragma unroll
-            for (int i = 0; i < D; ++i) K[i] = b * K[i] + digit[i];
-            parts *= b;
+            mult *= b;
         }
+        uint64_t root = rest; // < d^D < 2^64
+#pragma unroll
+        for (int i = D - 1; i >= 0; --i) {
+            K[i] += (root % d) * mult;
+            root /= d;
+        }
+        const uint64_t parts = mult;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
             h[i] = sd.h0[i] / (double)parts;
@@ -162,10 +167,10 @@ struct CubeState;
 template <class I, int D>
 struct CubeState<I, D, true> {
     typename I::P32 p;
-    __device__ __forceinline__ void set(const SlotDesc& sd, int level, uint64_t uid)
+    __device__ __forceinline__ void set(const SlotDesc& sd, int level, uint64_t uid, uint32_t uid_hi)
     {
         double lo[D], h[D];
-        corner<D>(sd, level, uid, lo, h);
+        corner<D>(sd, level, uid, uid_hi, lo, h);
         I::prep32(sd, lo, h, p);
     }
 };
@@ -174,10 +179,10 @@ template <class I, int D>
 struct CubeState<I, D, false> {
     typename I::P64 p;
     double lo[D], h24[D];
-    __device__ __forceinline__ void set(const SlotDesc& sd, int level, uint64_t uid)
+    __device__ __forceinline__ void set(const SlotDesc& sd, int level, uint64_t uid, uint32_t uid_hi)
     {
         double h[D];
-        corner<D>(sd, level, uid, lo, h);
+        corner<D>(sd, level, uid, uid_hi, lo, h);
 #pragma unroll
         for (int i = 0; i < D; ++i) h24[i] = ldexp(h[i], -24);
         I::prep64(sd, p);
@@ -236,6 +241,7 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
     decode();
     CubeState<I, D, FP32> cs;
     uint64_t uid = 0;
+    uint32_t uid_hi = 0;
     bool fresh = true; // the cube's state is to be (re)computed
 
     for (; u < uend; ++u) {
@@ -247,12 +253,13 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
         const int level = sg->level;
         if (fresh) {
             uid = a.uid[sg->cube_base + cl];
-            cs.set(*sd, level, uid);
+            uid_hi = a.uid_hi ? a.uid_hi[sg->cube_base + cl] : 0u;
+            cs.set(*sd, level, uid, uid_hi);
             fresh = false;
         }
 
         const uint32_t k0 = (uint32_t)sd->seed, k1 = (uint32_t)(sd->seed >> 32);
-        const uint32_t c1 = (uint32_t)trial | ((uint32_t)level << 8);
+        const uint32_t c1 = ctr_word1(trial, level, uid_hi);
         const uint32_t c2 = (uint32_t)uid, c3 = (uint32_t)(uid >> 32);
         const int64_t N = sd->samples;
         const int G = sd->groups;
@@ -268,9 +275,6 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
         // the allocator spill (up to 66% slower), and from D = kHalvesMinD
         // on the mask costs under 1%; those keep the one masked loop.
         constexpr bool kWholeLoop = D < kHalvesMinD && (W <= 5 || (W == 7 && D <= 6));
-        // A group's 4 values are summed in pairs, ((f0 + f1) + (f2 + f3)),
-        // before they join the running sum: one dependent FP64 add per group
-        // on the sum's chain instead of four.
         auto run = [&](auto ragged) {
             for (int j = 0; j < G; ++j) {
                 const int64_t g = g0 + (int64_t)j * 64;
@@ -278,23 +282,6 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
                 if (s0 >= N) break;
                 int nvalid = 4;
                 if constexpr (decltype(ragged)::value) nvalid = (int)min((int64_t)4, N - s0);
-                double p01 = 0.0, pcur = 0.0, q01 = 0.0, qcur = 0.0;
-                auto add = [&](int q, double fd) {
-                    if (q == 0 || q == 2) {
-                        pcur = fd;
-                        if constexpr (KEEP_S2) qcur = fd * fd;
-                    } else {
-                        pcur += fd;
-                        if constexpr (KEEP_S2) qcur = fma(fd, fd, qcur);
-                        if (q == 1) {
-                            p01 = pcur;
-                            if constexpr (KEEP_S2) q01 = qcur;
-                        } else {
-                            S1 += p01 + pcur;
-                            if constexpr (KEEP_S2) S2 += q01 + qcur;
-                        }
-                    }
-                };
                 group_samples<D>((uint32_t)g * (uint32_t)D, c1, c2, c3, k0, k1, [&](int q, const uint32_t* w) {
                     if constexpr (FP32) {
                         float v[D];
@@ -302,7 +289,9 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
                         for (int i = 0; i < D; ++i) v[i] = unit_interval_f32(w[i]);
                         float f = I::f32(cs.p, v);
                         if constexpr (decltype(ragged)::value) f = (q < nvalid) ? f : 0.0f;
-                        add(q, (double)f);
+                        const double fd = (double)f;
+                        S1 += fd;
+                        if constexpr (KEEP_S2) S2 = fma(fd, fd, S2);
                     } else {
                         double x[D];
                         // x = fma(h, (2*(w>>9)+1) 2^-24, lo) computed as
@@ -311,7 +300,8 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
                         for (int i = 0; i < D; ++i) x[i] = fma(cs.h24[i], (double)((w[i] >> 8) | 1u), cs.lo[i]);
                         double f = I::f64(cs.p, x);
                         if constexpr (decltype(ragged)::value) f = (q < nvalid) ? f : 0.0;
-                        add(q, f);
+                        S1 += f;
+                        if constexpr (KEEP_S2) S2 = fma(f, f, S2);
                     }
                 });
             }

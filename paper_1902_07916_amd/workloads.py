@@ -70,11 +70,10 @@ PAPER_RUNS = {
     "f2_ray": dict(f="f2", divisions=3, samples=10 ** 4, max_depth=3, sigma_mult=4.0,
                    ref="Numba-Ray version, Table 4: 3/axis, 1e4 points, 5 trials, depth 4, 4 sigma"),
     # the 12-D Gaussian of Table 4, at the 9-D run's parameters (the paper
-    # gives none of its own) but depth 3: with 3 parts per axis a depth-4
-    # tree has 3^48 sub-domains, more than 64-bit cube ids can name
-    "f2_12d_ray": dict(f="f2", dim=12, divisions=3, samples=10 ** 4, max_depth=2, sigma_mult=4.0,
-                       ref="Numba-Ray version, Table 4, 12-D: 3/axis, 1e4 points, 5 trials, depth 3 (paper: 4), "
-                           "4 sigma"),
+    # gives none of its own); with 3 parts per axis its depth-4 tree names
+    # 3^48 ~ 2^76 sub-domains, which takes cube ids past 64 bits
+    "f2_12d_ray": dict(f="f2", dim=12, divisions=3, samples=10 ** 4, max_depth=3, sigma_mult=4.0,
+                       ref="Numba-Ray version, Table 4, 12-D: 3/axis, 1e4 points, 5 trials, depth 4, 4 sigma"),
 }
 
 

@@ -62,12 +62,37 @@ FP32_TRIAL_TOL = 2e-5
 S_FLOOR = 2.0 ** -532
 
 
-def trial_tol(eval_, N):
+def trial_tol(eval_, N, w=None, level=0):
     """Per-trial bound relative to V * sum |f| / N from the summation: both
     sides sum the same N values in different orders, and a recursive sum is
     within (N - 1) u of the sum of |f| (u = 2^-53); FP32: FP32_TRIAL_TOL,
-    measured, covering the evaluation too."""
-    return (2 * N + 8) * U64 if eval_ == "fp64" else FP32_TRIAL_TOL
+    measured, covering the evaluation too, or the product peak's argument
+    conditioning at this level where that is larger (fp32_ppeak_error)."""
+    if eval_ == "fp64":
+        return (2 * N + 8) * U64
+    if w is not None and w["integrand"] == 3:
+        return max(FP32_TRIAL_TOL, fp32_ppeak_error(w, level))
+    return FP32_TRIAL_TOL
+
+
+def fp32_ppeak_error(w, level):
+    """Relative error bound of one FP32 product-peak value at a level.
+
+    The FP32 form evaluates prod 1 / (1 + u_i^2) with u_i = m_i v_i + a_i,
+    where m_i = c_i h_i and a_i (the cube's offset from the peak, scaled
+    by c_i) are rounded to FP32 once per cube and v_i is exact.  Then
+    |du_i| <= (|a_i| + |m_i| + |u_i|) 2^-24 <= (2 |u_i| + 2 |m_i|) 2^-24
+    (|a_i| <= |u_i| + |m_i| because v_i lies in (0, 1)), and the relative
+    change of 1 / (1 + u^2) is at most 2 |u| |du| / (1 + u^2), which with
+    |u| / (1 + u^2) <= 1/2 gives (4 + 2 |m_i|) 2^-24 per axis.  Add one
+    rounding for each fma, product and the reciprocal (2 D + 4).  The
+    width h_i at the level is the root width over split^level.  A sharp
+    peak (c h >> 1) is where this exceeds the measured FP32 bound."""
+    D = len(w["lower"])
+    c = np.abs(np.asarray(w["params"][:D], float))
+    h = (np.asarray(w["upper"], float) - np.asarray(w["lower"], float)) / w["divisions"]
+    h = h / float((w.get("split", 0) or 2) ** level)
+    return 2.0 ** -24 * (float(np.sum(4.0 + 2.0 * c * h)) + 2 * D + 4)
 
 
 def fp64_point_error(w):
@@ -131,27 +156,27 @@ def compare_tree(orc, w, r, eps, tol, report=None):
     Totals: integral within tol relative (or tol times the oracle's integral
     of |f| where the integral is near 0), std within tol relative."""
     p = oracle_problem(orc, w)
-    replay = [(L["uid"], L["sel"]) for L in r.trace]
+    replay = [(L["uid"], L["sel"], L["uid_hi"]) for L in r.trace]
     o = orc.integrate(p, replay=replay, band_eps=eps)
     assert o.status == 0 and r.status == 0
     assert len(o.levels) == r.levels_run
     eval_ = w.get("eval", "fp64")
     N, n1 = int(w["samples"]), int(w["trials"])
-    tI = trial_tol(eval_, N)
     rho, alpha = fp64_point_error(w) if eval_ == "fp64" else (0.0, 0.0)
     stats = dict(dI=0.0, ds=0.0, dthr=0.0)
     for l, (Lo, Lg) in enumerate(zip(o.levels, r.trace)):
         assert Lg["n"] == Lo.n
         assert len(Lg["uid"]) == Lg["n"], "trace capacity too small"
         assert np.array_equal(Lg["uid"], Lo.uid), "level %d list differs" % l
-        V = orc.bounds(p, l, int(Lo.uid[0]))[2]
+        assert np.array_equal(Lg["uid_hi"], Lo.uid_hi), "level %d list differs (id bits above 64)" % l
+        V = orc.bounds(p, l, int(Lo.uid[0]) | (int(Lo.uid_hi[0]) << 64))[2]
         Ig = V * (np.asarray(Lg["S1"]) / N)
         dI = np.abs(Ig - Lo.I).max(axis=1)
         scale = n1 * Lo.sa
         Imax = np.abs(Lo.I).max(axis=1)
         with np.errstate(divide="ignore", invalid="ignore"):
             stats["dI"] = max(stats["dI"], float(np.nanmax(np.where(scale > 0, dI / scale, 0.0))))
-        bound_I = (tI + rho) * scale + V * alpha
+        bound_I = (trial_tol(eval_, N, w, l) + rho) * scale + V * alpha
         worst = int(np.argmax(dI - bound_I))
         assert np.all(dI <= bound_I), ("level %d trial sums" % l, worst, dI[worst], bound_I[worst], scale[worst])
         slack = 4 * (n1 + 2) * U64 * Imax
@@ -218,7 +243,7 @@ def check_levels_sampled(orc, w, r, n_sample, m_tol, m_floor=0.0, seed=0):
         if not last:
             idx += list(np.nonzero(sel)[0][:64])
         for i in np.unique(idx):
-            st, I, m, s, sa = orc.cube(p, l, int(L["uid"][i]))
+            st, I, m, s, sa = orc.cube(p, l, int(L["uid"][i]) | (int(L["uid_hi"][i]) << 64))
             assert st == 0
             assert abs(L["m"][i] - m) <= m_tol * sa + m_floor, (l, i, L["m"][i], m, sa)
             assert abs(L["s"][i] - s) <= m_tol * sa * 10 + 1e-9 * s + m_floor, (l, i, L["s"][i], s)
@@ -235,10 +260,16 @@ def check_levels_sampled(orc, w, r, n_sample, m_tol, m_floor=0.0, seed=0):
             assert len(band) == 0, "cubes within %.3g of the threshold: %s" % (thr_eps, band)
             assert int(sel.sum()) == r.selected_per_level[l]
             parents = L["uid"][sel]
+            parents_hi = L["uid_hi"][sel]
+            # ids below 2^64: children as uint64 arithmetic (wraps past 2^64,
+            # compared with the low bits); every parent: the oracle's children
             kids = (parents[:, None] * np.uint64(kids_n) + np.arange(kids_n, dtype=np.uint64)[None, :]).ravel()
             assert np.array_equal(r.trace[l + 1]["uid"], kids)
-            for j in rng.integers(0, max(len(parents), 1), min(4, len(parents))):
-                assert np.array_equal(orc.children(int(parents[j]), D, b), kids[j * kids_n:(j + 1) * kids_n])
+            picks = range(len(parents)) if len(parents) <= 8 else rng.integers(0, len(parents), 8)
+            for j in picks:
+                clo, chi = orc.children_w(int(parents[j]) | (int(parents_hi[j]) << 64), D, b)
+                assert np.array_equal(clo, kids[j * kids_n:(j + 1) * kids_n])
+                assert np.array_equal(chi, r.trace[l + 1]["uid_hi"][j * kids_n:(j + 1) * kids_n])
             keep = ~sel
         else:
             keep = np.ones(L["n"], bool)

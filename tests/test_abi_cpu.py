@@ -63,7 +63,7 @@ def test_invalid_arguments_are_rejected_before_any_device_call(lib):
            # k-way split and threshold scope (Sec. 2.1 variants)
            dict(split=1), dict(split=65), dict(threshold_scope=2), dict(threshold_scope=-1),
            dict(split=64, params=[0.2, 1.0] + [0.0] * 5, lower=[0.0] * 5, upper=[1.0] * 5),
-           dict(split=3, max_depth=9, divisions=2, params=[0.2, 1.0] + [0.0] * 5, lower=[0.0] * 5,
+           dict(split=3, max_depth=12, divisions=2, params=[0.2, 1.0] + [0.0] * 5, lower=[0.0] * 5,
                 upper=[1.0] * 5)]
     for b in bad:
         r = _req(**b)

@@ -149,3 +149,23 @@ def test_serving_cancel_and_errors(zi):
         zi.poll(t)        # collected already
     with pytest.raises(ZmcError):
         zi.submit(make_request("gauss", [0.1], [0.0], [1.0], 2, 16, 3, 1, 1.0, 1))  # wrong params
+
+
+def test_small_level_launch_matches_tiled_path(zi):
+    """A level whose segments are all one tile (<= 1024 cubes) runs as one
+    launch; the same requests batched with a large one (several tiles) go
+    through the per-tile kernels.  Both give bitwise the same results, for
+    both threshold scopes and in both precisions."""
+    from paper_1902_07916_amd import make_request
+    big = make_request("genz_gauss", [2.0] * 4 + [0.3] * 4, [0.0] * 4, [1.0] * 4, 7, 256, 3, 2, 1.0, 5, eval="fp32")
+    small = []
+    for i, (ev, scope) in enumerate((("fp32", 0), ("fp64", 0), ("fp32", 1), ("fp64", 1))):
+        small.append(make_request("gauss", [0.15, 1.0, 0.2, 0.6, 0.4], [0.0] * 3, [1.0] * 3, 5, 300 + 4 * i, 4, 2,
+                                  0.5, 11 + i, eval=ev, threshold_scope=scope))
+    batch = zi.integrate_batch([big] + small)
+    assert batch[0].cubes_per_level[0] == 7 ** 4 > 1024
+    for q, b in zip(small, batch[1:]):
+        alone = zi.integrate_request(q)
+        assert alone.status == 0 and max(alone.cubes_per_level) <= 1024
+        assert len(alone.cubes_per_level) == 3 and alone.selected_per_level[0] > 0
+        assert _same(b, alone), (b, alone)

@@ -167,3 +167,18 @@ def test_deterministic_run_to_run(zi):
     a = zi.integrate(**w)
     b = zi.integrate(**w)
     assert a.integral == b.integral and a.std == b.std and a.cubes_per_level == b.cubes_per_level
+
+
+@pytest.mark.parametrize("eval_", ["fp64", "fp32"])
+def test_tree_through_wide_ids(zi, orc, eval_):
+    """Cube ids past 64 bits (bits 64..83 in a second array and in counter
+    word 1): a narrow 6-D product peak followed by bisection to level 11
+    (12 root bits + 6 per split), whose levels 10 and 11 hold such ids;
+    the whole tree against the oracle, id lists bit-exact."""
+    prm = [1e3] * 6 + [0.3141, 0.2718, 0.5772, 0.6931, 0.4142, 0.7320]
+    w = dict(integrand=3, params=prm, lower=[0.0] * 6, upper=[1.0] * 6, divisions=4, samples=256, trials=4,
+             max_depth=11, sigma_mult=3.0, seed=3, eval=eval_)
+    r = zi.integrate(**w, trace=True)
+    assert r.levels_run == 12
+    assert r.trace[10]["uid_hi"].max() > 0 and r.trace[11]["uid_hi"].max() > 0
+    _compare_tree(orc, w, r, EPS64 if eval_ == "fp64" else EPS32, 1e-6 if eval_ == "fp64" else 1e-4)

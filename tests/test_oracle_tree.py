@@ -117,7 +117,11 @@ def test_validation(orc):
     bad = [dict(dim=0, params=[0.2, 1.0]), dict(dim=17), dict(lower=1.0, upper=1.0), dict(divisions=0),
            dict(samples=0), dict(trials=1), dict(trials=256), dict(max_depth=-1), dict(max_depth=16),
            dict(sigma_mult=-1.0), dict(sigma_mult=float("nan")), dict(params=[0.2, 1.0]),
-           dict(integrand=99), dict(dim=16, divisions=2, max_depth=4, params=[0.2, 1.0] + [0.0] * 16),
+           dict(integrand=99), dict(dim=16, divisions=2, max_depth=5, params=[0.2, 1.0] + [0.0] * 16),
+           # ids past 84 bits (3^12 roots, three 3^12-way splits: 2^76 is fine, four: 2^95 not)
+           dict(dim=12, divisions=3, split=3, max_depth=4, params=[0.2, 1.0] + [0.0] * 12),
+           # lattice cells per axis past 64 bits though ids fit 84 (2 * 64^11 = 2^67)
+           dict(dim=1, divisions=2, split=64, max_depth=11, params=[0.2, 1.0, 0.0]),
            dict(integrand=orc.MONOMIAL, params=[1.5, 2.0])]
     for b in bad:
         kw = dict(good)
@@ -125,6 +129,13 @@ def test_validation(orc):
         assert orc.validate(orc.problem(**kw)) == orc.EINVAL, b
     r = orc.integrate(orc.problem(**dict(good, trials=1)))
     assert r.status == orc.EINVAL
+    # ids of up to 84 bits are accepted: 16 root bits + 4 x 16, and 3^12 * (3^12)^3
+    for ok in (dict(dim=16, divisions=2, max_depth=4, params=[0.2, 1.0] + [0.0] * 16),
+               dict(dim=12, divisions=3, split=3, max_depth=3, params=[0.2, 1.0] + [0.0] * 12),
+               dict(dim=1, divisions=2, split=64, max_depth=10, params=[0.2, 1.0, 0.0])):
+        kw = dict(good)
+        kw.update(ok)
+        assert orc.validate(orc.problem(**kw)) == 0, ok
 
 
 def test_nonfinite_integrand_fails_run(orc):

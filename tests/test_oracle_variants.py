@@ -84,6 +84,8 @@ def test_variant_validation(orc):
         kw = dict(base)
         kw.update(bad)
         assert orc.validate(orc.problem(**kw)) == orc.EINVAL, bad
-    # uid range with b = 5: 4^2 * 25^12 < 2^64 <= 4^2 * 25^13
-    assert orc.validate(orc.problem(**dict(base, max_depth=12), split=5)) == 0
-    assert orc.validate(orc.problem(**dict(base, max_depth=13), split=5)) == orc.EINVAL
+    # id range (84 bits) with b = 5 in 4-D: 4^4 * 625^8 < 2^84 <= 4^4 * 625^9
+    b4 = dict(base, dim=4, params=[0.2, 1.0] + [0.0] * 4)
+    assert 4 ** 4 * 625 ** 8 < 2 ** 84 <= 4 ** 4 * 625 ** 9
+    assert orc.validate(orc.problem(**dict(b4, max_depth=8), split=5)) == 0
+    assert orc.validate(orc.problem(**dict(b4, max_depth=9), split=5)) == orc.EINVAL
