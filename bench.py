@@ -106,7 +106,7 @@ WORKLOADS = {
 # level kernels' arguments and launchers in zmc_kernels.hpp do not enter it).
 KERNEL_SOURCES = ("paper_1902_07916_amd/build.py", "paper_1902_07916_amd/csrc/zmc_sample.hip",
                   "paper_1902_07916_amd/csrc/zmc_sample_core.hpp", "paper_1902_07916_amd/csrc/zmc_integrands.hpp",
-                  "paper_1902_07916_amd/csrc/zmc_device.hpp")
+                  "paper_1902_07916_amd/csrc/zmc_device.hpp", "paper_1902_07916_amd/csrc/zmc_tune_gfx950.json")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sample_kernel.json")
 
 
@@ -304,15 +304,25 @@ def run_serve(a, duration=None) -> dict:
     res = [zi.poll(tk, wait=True) for tk in tickets]
     dt = time.perf_counter() - t0
     st = zi.serve_stats()
-    zi.close()
     lat = [r.latency_ms for r in res]
+    # p99 latency in the stream by the request's own work: its engine time
+    # when it runs alone afterwards (same lane arena, nothing beside it)
+    own = []
+    for rq in reqs:
+        own.append(sum(zi.integrate_request(rq).ms_per_level))
+    zi.close()
+    by_own = {}
+    for name, lo, hi in (("own<0.2ms", 0.0, 0.2), ("0.2-1ms", 0.2, 1.0), ("1-5ms", 1.0, 5.0), ("own>=5ms", 5.0, 1e30)):
+        sel = [x for x, o in zip(lat, own) if lo <= o < hi]
+        by_own[name] = {"requests": len(sel), "p99_ms": percentile(sel, 0.99) if sel else None}
     return {"requests": len(res), "offered_rate": a.rate, "duration_s": duration, "wall_s": dt,
             "integrals_per_s": len(res) / dt, "p50_ms": percentile(lat, 0.5), "p99_ms": percentile(lat, 0.99),
             "max_ms": max(lat), "rtol_met": sum(bool(r.flags & 2) for r in res) / len(res),
             "status_ok": sum(r.status == 0 for r in res), "samples": sum(r.n_samples for r in res),
             "samples_per_s": sum(r.n_samples for r in res) / dt, "levels_stepped": st["levels"],
             "level_cost_beyond_sampling_ms": {"p50": percentile(over, 0.5), "p90": percentile(over, 0.9),
-                                              "levels": len(over)}}
+                                              "levels": len(over)},
+            "p99_by_own_work": by_own}
 
 
 # The paper's own timings on its hardware (Tables 1-4), seconds per run.
@@ -356,7 +366,10 @@ def run_paper(a) -> dict:
                             "samples_per_run": statistics.mean(r.n_samples for r in res),
                             "samples_per_s": statistics.mean(r.n_samples for r in res) / statistics.mean(times),
                             "levels_seed1": res[0].cubes_per_level[:res[0].levels_run],
-                            "truncated": sum(bool(r.flags & 1) for r in res)}
+                            "values": vals,
+                            "levels_per_seed": [r.cubes_per_level[:r.levels_run] for r in res],
+                            "truncated": sum(bool(r.flags & 1) for r in res),
+                            "fp32_range_flagged": sum(bool(r.flags & 4) for r in res)}
                 print("%s %s: mean %.6g spread %.3g, %.4f s/run, levels %s" % (
                     name, key, row[key]["mean"], row[key]["spread"], row[key]["s_per_run"],
                     row[key]["levels_seed1"]), file=sys.stderr, flush=True)

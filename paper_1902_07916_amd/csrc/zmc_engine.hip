@@ -42,11 +42,13 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 constexpr int64_t kFuseMaxTiles = 256;
 
 // Packed per-level tables: segments at 0, running totals, bucket segments,
-// per-segment flags (uploaded as zeros).
+// per-segment flags (uploaded as zeros), then the segments of the previous
+// level's spawn and of the new roots (at most two per slot).
 size_t prev_offset(int ns) { return align256((size_t)ns * sizeof(Segment)); }
 size_t bseg_offset(int ns) { return prev_offset(ns) + align256((size_t)ns * sizeof(double2)); }
 size_t flags_offset(int ns) { return bseg_offset(ns) + align256((size_t)ns * sizeof(BSeg)); }
-size_t table_bytes(int max_segs) { return flags_offset(max_segs) + (size_t)max_segs * sizeof(int32_t); }
+size_t next_offset(int ns) { return align256(flags_offset(ns) + (size_t)ns * sizeof(int32_t)); }
+size_t table_bytes(int max_segs) { return next_offset(max_segs) + 2 * (size_t)max_segs * sizeof(Segment); }
 
 // Built-in occupancy variant per bucket (index into kWaveHints), measured by
 // the tuner on gfx950 and embedded at build time; a tuning file overrides it.
@@ -166,7 +168,6 @@ int Engine::setup(char* base, size_t bytes, int max_slots, const TileTable* tile
     tab_bytes_ = table_bytes(max_slots);
     d_tab_ = carve(tab_bytes_);
     d_stats_ = (SegStats*)carve(sizeof(SegStats) * max_slots);
-    d_rootsegs_ = (Segment*)carve(sizeof(Segment) * max_slots);
     d_seg_count_ = (int32_t*)carve(sizeof(int32_t) * max_slots);
     off = (off + 255) & ~(size_t)255;
     if (off + (16u << 20) > bytes) {
@@ -178,8 +179,7 @@ int Engine::setup(char* base, size_t bytes, int max_slots, const TileTable* tile
     ZMC_HIP(hipMemset(d_seg_count_, 0, sizeof(int32_t) * max_slots));
     ZMC_HIP(hipHostMalloc((void**)&h_slots_, sizeof(SlotDesc) * max_slots, hipHostMallocDefault));
     ZMC_HIP(hipHostMalloc((void**)&h_tab_, tab_bytes_, hipHostMallocDefault));
-    ZMC_HIP(hipHostMalloc((void**)&h_segs2_, sizeof(Segment) * max_slots, hipHostMallocDefault));
-    ZMC_HIP(hipHostMalloc((void**)&h_rootsegs_, sizeof(Segment) * max_slots, hipHostMallocDefault));
+    ZMC_HIP(hipHostMalloc((void**)&h_nextsegs_, sizeof(Segment) * 2 * max_slots, hipHostMallocDefault));
     // the decision kernel writes each level's per-segment records straight
     // into this mapped host buffer, read after the level's synchronisation
     ZMC_HIP(hipHostMalloc((void**)&h_stats_, sizeof(SegStats) * max_slots, hipHostMallocMapped));
@@ -195,12 +195,12 @@ int Engine::setup(char* base, size_t bytes, int max_slots, const TileTable* tile
 
 void Engine::teardown()
 {
-    void* hs[] = {h_slots_, h_tab_, h_segs2_, h_rootsegs_, h_stats_};
+    void* hs[] = {h_slots_, h_tab_, h_nextsegs_, h_stats_};
     for (void* p : hs)
         if (p) (void)hipHostFree(p);
     h_slots_ = nullptr;
     h_tab_ = nullptr;
-    h_segs_ = h_segs2_ = h_rootsegs_ = nullptr;
+    h_segs_ = h_nextsegs_ = nullptr;
     h_bsegs_ = nullptr;
     h_stats_ = d_hstats_ = nullptr;
     h_prev_ = nullptr;
@@ -462,8 +462,22 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
     int32_t* h_flags = (int32_t*)(h_tab_ + flags_offset(ns));
     int32_t* d_flags = (int32_t*)(d_tab_ + flags_offset(ns));
     memset(h_flags, 0, (size_t)ns * sizeof(int32_t));
-    ZMC_HIP(hipMemcpyAsync(d_tab_, h_tab_, flags_offset(ns) + (size_t)ns * sizeof(int32_t), hipMemcpyHostToDevice,
-                           st));
+    size_t up = flags_offset(ns) + (size_t)ns * sizeof(int32_t);
+    if (pend_next_) {
+        const size_t off = next_offset(ns);
+        memcpy(h_tab_ + off, h_nextsegs_, (size_t)pend_n_up_ * sizeof(Segment));
+        up = off + (size_t)pend_n_up_ * sizeof(Segment);
+    }
+    ZMC_HIP(hipMemcpyAsync(d_tab_, h_tab_, up, hipMemcpyHostToDevice, st));
+    if (pend_next_) {
+        // this level's list: children of the last level's selected cubes,
+        // then the roots of new integrals
+        Segment* d_next = (Segment*)(d_tab_ + next_offset(ns));
+        if (pend_la_.n_segs > 0) pend_la_.segs = d_next;
+        if (pend_ra_.n_segs > 0) pend_ra_.segs = d_next + pend_n_spawn_segs_;
+        pend_next_ = false;
+        ZMC_HIP(launch_next_list(pend_la_, pend_ra_, st));
+    }
     ZMC_HIP(hipEventRecord(ev_sample0_, st));
     int n_launch = 0;
     for (const Launch& L : launches) {
@@ -568,7 +582,8 @@ int Engine::step(hipStream_t st, const std::vector<LiveSeg>& live, uint64_t* cur
 }
 
 // Lay out the next list: children of every continuing segment (in list
-// order), then the roots of newly admitted integrals; launch spawn and roots.
+// order), then the roots of newly admitted integrals.  Their segments go up
+// with the next level's table and one launch writes both (step()).
 int Engine::next_list(hipStream_t st, std::vector<LiveSeg>& live, const std::vector<int>& split,
                       const std::vector<LiveSeg>& fresh, uint64_t*& cur_uid, int& cur_side)
 {
@@ -576,23 +591,25 @@ int Engine::next_list(hipStream_t st, std::vector<LiveSeg>& live, const std::vec
     int64_t total = 0;
     const int ns = (int)live.size();
     bool any_split = false;
-    for (int i = 0; i < ns; ++i) {
-        h_segs2_[i] = h_segs_[i];
-        h_segs2_[i].do_split = 0;
-        h_segs2_[i].child_base = 0;
+    for (int i = 0; i < ns; ++i) any_split |= split[i] != 0;
+    const int n_spawn_segs = any_split ? ns : 0;
+    Segment* spawn_segs = h_nextsegs_;
+    Segment* root_segs = h_nextsegs_ + n_spawn_segs;
+    for (int i = 0; i < n_spawn_segs; ++i) {
+        spawn_segs[i] = h_segs_[i];
+        spawn_segs[i].do_split = 0;
+        spawn_segs[i].child_base = 0;
         if (split[i]) {
             HostSlot& hs = slots_[live[i].slot];
             const int64_t nc = h_stats_[i].n_sel * kids_of(hs.req);
-            h_segs2_[i].do_split = 1;
-            h_segs2_[i].child_base = total;
+            spawn_segs[i].do_split = 1;
+            spawn_segs[i].child_base = total;
             total += nc;
             nxt.push_back({live[i].slot, nc});
-            any_split = true;
         }
     }
-    const int64_t root_base = total;
     for (size_t j = 0; j < fresh.size(); ++j) {
-        Segment& g = h_rootsegs_[j];
+        Segment& g = root_segs[j];
         memset(&g, 0, sizeof(g));
         g.slot = fresh[j].slot;
         g.cube_base = total;
@@ -600,7 +617,6 @@ int Engine::next_list(hipStream_t st, std::vector<LiveSeg>& live, const std::vec
         total += fresh[j].n_cubes;
         nxt.push_back(fresh[j]);
     }
-    (void)root_base;
     const int other = cur_side ^ 1;
     uint64_t* next_uid = nullptr;
     uint32_t* next_hi = nullptr;
@@ -614,35 +630,31 @@ int Engine::next_list(hipStream_t st, std::vector<LiveSeg>& live, const std::vec
             return ZMC_ENOMEM;
         }
     }
+    // the upload and the launch go with the next level's table (step())
+    pend_n_up_ = n_spawn_segs + (int)fresh.size();
+    pend_n_spawn_segs_ = n_spawn_segs;
+    memset(&pend_la_, 0, sizeof(pend_la_));
+    memset(&pend_ra_, 0, sizeof(pend_ra_));
     if (any_split) {
-        ZMC_HIP(hipMemcpyAsync(d_segs_, h_segs2_, ns * sizeof(Segment), hipMemcpyHostToDevice, st));
-        LevelArgs la;
-        memset(&la, 0, sizeof(la));
-        la.slots = d_slots_;
-        la.segs = d_segs_;
-        la.n_segs = ns;
-        la.n_tiles = n_tiles_;
-        la.uid = cur_uid;
-        la.uid_hi = cur_hi_;
-        la.sel = cur_sel_;
-        la.tiles = cur_tiles_;
-        la.next_uid = next_uid;
-        la.next_uid_hi = next_hi;
-        ZMC_HIP(launch_spawn(la, st));
+        pend_la_.slots = d_slots_;
+        pend_la_.n_segs = ns;
+        pend_la_.n_tiles = n_tiles_;
+        pend_la_.uid = cur_uid;
+        pend_la_.uid_hi = cur_hi_;
+        pend_la_.sel = cur_sel_;
+        pend_la_.tiles = cur_tiles_;
+        pend_la_.next_uid = next_uid;
+        pend_la_.next_uid_hi = next_hi;
     }
     if (!fresh.empty()) {
-        ZMC_HIP(hipMemcpyAsync(d_rootsegs_, h_rootsegs_, fresh.size() * sizeof(Segment), hipMemcpyHostToDevice,
-                               st));
-        RootArgs ra;
-        ra.segs = d_rootsegs_;
-        ra.n_segs = (int)fresh.size();
+        pend_ra_.n_segs = (int)fresh.size();
         int64_t mx = 1;
         for (auto& f : fresh) mx = std::max(mx, f.n_cubes);
-        ra.blocks_per_seg = (int)std::min<int64_t>(64, ceil_div(mx, 4096));
-        ra.uid = next_uid;
-        ra.uid_hi = next_hi;
-        ZMC_HIP(launch_roots(ra, st));
+        pend_ra_.blocks_per_seg = (int)std::min<int64_t>(64, ceil_div(mx, 4096));
+        pend_ra_.uid = next_uid;
+        pend_ra_.uid_hi = next_hi;
     }
+    pend_next_ = pend_n_up_ > 0;
     // levels advance for the split segments
     for (int i = 0; i < ns; ++i)
         if (split[i]) slots_[live[i].slot].level += 1;
@@ -665,6 +677,7 @@ int Engine::drive(hipStream_t st, Admission& adm, zmc_trace* trace, const std::a
     std::vector<LiveSeg> live;
     uint64_t* cur_uid = nullptr;
     cur_hi_ = nullptr;
+    pend_next_ = false;
     int cur_side = 0;
     arena_.reset(0);
     arena_.reset(1);
@@ -708,6 +721,7 @@ int Engine::drive(hipStream_t st, Admission& adm, zmc_trace* trace, const std::a
                 split.clear();
                 cur_uid = nullptr;
                 cur_hi_ = nullptr;
+                pend_next_ = false;
                 arena_.reset(0);
                 arena_.reset(1);
                 if (rc == ZMC_EDEVICE) return rc;
@@ -781,6 +795,7 @@ int Engine::drive(hipStream_t st, Admission& adm, zmc_trace* trace, const std::a
             live.clear();
             cur_uid = nullptr;
             cur_hi_ = nullptr;
+            pend_next_ = false;
             arena_.reset(0);
             arena_.reset(1);
             continue;
@@ -847,6 +862,7 @@ int Engine::cube_estimates(const zmc_request& req, int level, const uint64_t* ui
     uint64_t* d_uid = (uint64_t*)arena_.alloc(1, (size_t)n * 8);
     if (!d_uid) return ZMC_ENOMEM;
     cur_hi_ = nullptr; // ids given here are below 2^64
+    pend_next_ = false;
     ZMC_HIP(hipMemcpyAsync(d_uid, uids, (size_t)n * 8, hipMemcpyHostToDevice, st));
     std::vector<LiveSeg> live{{0, n}};
     rc = step(st, live, d_uid, 0, nullptr, true, S1 != nullptr || S2 != nullptr);

@@ -189,7 +189,6 @@ private:
     int32_t* d_seg_count_ = nullptr;
     SegStats* d_hstats_ = nullptr;
     Segment* d_segs_ = nullptr;
-    Segment* d_rootsegs_ = nullptr;
     BSeg* d_bsegs_ = nullptr;
     SegStats* d_stats_ = nullptr;
     double2* d_prev_ = nullptr;
@@ -197,8 +196,7 @@ private:
     // has been synchronised past its previous upload)
     SlotDesc* h_slots_ = nullptr;
     Segment* h_segs_ = nullptr;
-    Segment* h_segs2_ = nullptr;
-    Segment* h_rootsegs_ = nullptr;
+    Segment* h_nextsegs_ = nullptr;
     BSeg* h_bsegs_ = nullptr;
     SegStats* h_stats_ = nullptr;
     double2* h_prev_ = nullptr;
@@ -217,6 +215,14 @@ private:
     double* cur_S2_ = nullptr;
     int64_t n_list_ = 0;
     int64_t n_tiles_ = 0;
+    // the next list's spawn / roots launch, laid out by next_list and issued
+    // by the next step() after its table upload, which carries these
+    // segments too (one copy per level)
+    bool pend_next_ = false;
+    LevelArgs pend_la_{};
+    RootArgs pend_ra_{};
+    int pend_n_up_ = 0;
+    int pend_n_spawn_segs_ = 0;
     // GPU time of the last level's sampling launches
     hipEvent_t ev_sample0_ = nullptr, ev_sample1_ = nullptr;
     float last_sample_ms_ = 0.0f;

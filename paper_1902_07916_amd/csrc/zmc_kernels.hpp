@@ -79,8 +79,9 @@ hipError_t launch_level_small(const LevelArgs& a, hipStream_t st);
 hipError_t launch_threshold(const LevelArgs& a, hipStream_t st);
 hipError_t launch_group_threshold(const LevelArgs& a, hipStream_t st);
 hipError_t launch_select(const LevelArgs& a, hipStream_t st);
-hipError_t launch_spawn(const LevelArgs& a, hipStream_t st);
-hipError_t launch_roots(const RootArgs& a, hipStream_t st);
+// Spawn (a.n_tiles blocks, none when 0) and roots (ra.n_segs segments, none
+// when 0) in one launch.
+hipError_t launch_next_list(const LevelArgs& a, const RootArgs& ra, hipStream_t st);
 hipError_t launch_debug_philox(uint32_t k0, uint32_t k1, const uint32_t* ctr, uint32_t* out, int64_t n,
                                hipStream_t st);
 hipError_t launch_debug_points(const SlotDesc* sd, int level, uint64_t uid, int trial, int64_t s0, int64_t n,

@@ -552,12 +552,12 @@ __global__ __launch_bounds__(kLevelThreads) void level_small_kernel(const LevelA
 }
 
 // ---- spawn: children of the selected cubes, in list order ------------------
-__global__ __launch_bounds__(kLevelThreads) void spawn_kernel(const LevelArgs a)
+// One block per tile of the finished level.
+__device__ void spawn_tile(const LevelArgs& a, int64_t tile)
 {
     __shared__ uint64_t list[kTileCubes];
     __shared__ uint32_t list_hi[kTileCubes];
     __shared__ int shf[kWaves];
-    const int64_t tile = blockIdx.x;
     const int si = seg_of_tile(a.segs, a.n_segs, tile);
     const Segment& sg = a.segs[si];
     if (!sg.do_split) return;
@@ -604,16 +604,28 @@ __global__ __launch_bounds__(kLevelThreads) void spawn_kernel(const LevelArgs a)
 }
 
 // ---- roots: uid = r for the d^D cubes of a newly admitted integral ----------
-__global__ __launch_bounds__(kLevelThreads) void roots_kernel(const RootArgs a)
+__device__ void roots_block(const RootArgs& a, int blk)
 {
-    const int si = blockIdx.x / a.blocks_per_seg;
-    const int part = blockIdx.x % a.blocks_per_seg;
+    const int si = blk / a.blocks_per_seg;
+    const int part = blk % a.blocks_per_seg;
     const Segment& sg = a.segs[si];
     for (int64_t r = (int64_t)part * kLevelThreads + threadIdx.x; r < sg.n_cubes;
          r += (int64_t)a.blocks_per_seg * kLevelThreads) {
         a.uid[sg.cube_base + r] = (uint64_t)r;
         if (a.uid_hi) a.uid_hi[sg.cube_base + r] = 0u;
     }
+}
+
+// The next list in one launch: the first n_spawn blocks spawn children (one
+// per tile of the finished level), the rest write roots of new integrals.
+__global__ __launch_bounds__(kLevelThreads) void next_list_kernel(const LevelArgs a, const RootArgs ra,
+                                                                  int64_t n_spawn)
+{
+    const int64_t b = blockIdx.x;
+    if (b < n_spawn)
+        spawn_tile(a, b);
+    else
+        roots_block(ra, (int)(b - n_spawn));
 }
 
 // ---- debug entry points ------------------------------------------------------
@@ -689,17 +701,13 @@ hipError_t launch_select(const LevelArgs& a, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_spawn(const LevelArgs& a, hipStream_t st)
+hipError_t launch_next_list(const LevelArgs& a, const RootArgs& ra, hipStream_t st)
 {
-    if (a.n_tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL(spawn_kernel, dim3((unsigned)a.n_tiles), dim3(kLevelThreads), 0, st, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_roots(const RootArgs& a, hipStream_t st)
-{
-    if (a.n_segs <= 0) return hipSuccess;
-    hipLaunchKernelGGL(roots_kernel, dim3(a.n_segs * a.blocks_per_seg), dim3(kLevelThreads), 0, st, a);
+    const int64_t n_spawn = a.n_tiles > 0 ? a.n_tiles : 0;
+    const int64_t n_roots = ra.n_segs > 0 ? (int64_t)ra.n_segs * ra.blocks_per_seg : 0;
+    if (n_spawn + n_roots <= 0) return hipSuccess;
+    hipLaunchKernelGGL(next_list_kernel, dim3((unsigned)(n_spawn + n_roots)), dim3(kLevelThreads), 0, st, a, ra,
+                       n_spawn);
     return hipGetLastError();
 }
 

@@ -274,24 +274,39 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
         // the 7- and 8-wave variants from D = 7 (8-wave: from D = 5) it made
         // the allocator spill (up to 66% slower), and from D = kHalvesMinD
         // on the mask costs under 1%; those keep the one masked loop.
+        // In FP32 evaluation up to D = 3, a chunk holding G * 256 points or
+        // more (every lane has G whole groups) also drops the per-lane exit
+        // test: a wave-uniform trip count.  From D = 4 on, and in FP64, that
+        // loop took more registers than it saved instructions (one wave per
+        // SIMD less in several buckets).
+        // FP32 evaluation adds a group's 4 values in FP32 (in point order)
+        // and the group's sum in FP64: one conversion and one FP64 add per
+        // group instead of per point.
         constexpr bool kWholeLoop = D < kHalvesMinD && (W <= 5 || (W == 7 && D <= 6));
-        auto run = [&](auto ragged) {
+        constexpr bool kUniformLoop = FP32 && D <= 3;
+        auto run = [&](auto masked, auto tested) {
+            constexpr bool kMasked = decltype(masked)::value;
             for (int j = 0; j < G; ++j) {
                 const int64_t g = g0 + (int64_t)j * 64;
-                const int64_t s0 = 4 * g;
-                if (s0 >= N) break;
                 int nvalid = 4;
-                if constexpr (decltype(ragged)::value) nvalid = (int)min((int64_t)4, N - s0);
+                if constexpr (decltype(tested)::value) {
+                    const int64_t s0 = 4 * g;
+                    if (s0 >= N) break;
+                    if constexpr (kMasked) nvalid = (int)min((int64_t)4, N - s0);
+                }
+                float gs = 0.0f;
                 group_samples<D>((uint32_t)g * (uint32_t)D, c1, c2, c3, k0, k1, [&](int q, const uint32_t* w) {
                     if constexpr (FP32) {
                         float v[D];
 #pragma unroll
                         for (int i = 0; i < D; ++i) v[i] = unit_interval_f32(w[i]);
                         float f = I::f32(cs.p, v);
-                        if constexpr (decltype(ragged)::value) f = (q < nvalid) ? f : 0.0f;
-                        const double fd = (double)f;
-                        S1 += fd;
-                        if constexpr (KEEP_S2) S2 = fma(fd, fd, S2);
+                        if constexpr (kMasked) f = (q < nvalid) ? f : 0.0f;
+                        gs = q == 0 ? f : gs + f;
+                        if constexpr (KEEP_S2) {
+                            const double fd = (double)f;
+                            S2 = fma(fd, fd, S2);
+                        }
                     } else {
                         double x[D];
                         // x = fma(h, (2*(w>>9)+1) 2^-24, lo) computed as
@@ -299,18 +314,23 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
 #pragma unroll
                         for (int i = 0; i < D; ++i) x[i] = fma(cs.h24[i], (double)((w[i] >> 8) | 1u), cs.lo[i]);
                         double f = I::f64(cs.p, x);
-                        if constexpr (decltype(ragged)::value) f = (q < nvalid) ? f : 0.0;
+                        if constexpr (kMasked) f = (q < nvalid) ? f : 0.0;
                         S1 += f;
                         if constexpr (KEEP_S2) S2 = fma(f, f, S2);
                     }
                 });
+                if constexpr (FP32) S1 += (double)gs;
             }
         };
-        if constexpr (kWholeLoop) {
-            if ((N & 3) == 0) run(BoolTag<false>{});
-            else run(BoolTag<true>{});
+        if constexpr (kWholeLoop && kUniformLoop) {
+            const int64_t left = N - (int64_t)chunk * G * 256; // this chunk's points onward (wave-uniform)
+            if (left >= (int64_t)G * 256) run(BoolTag<false>{}, BoolTag<false>{});
+            else run(BoolTag<true>{}, BoolTag<true>{});
+        } else if constexpr (kWholeLoop) {
+            if ((N & 3) == 0) run(BoolTag<false>{}, BoolTag<true>{});
+            else run(BoolTag<true>{}, BoolTag<true>{});
         } else {
-            run(BoolTag<true>{});
+            run(BoolTag<true>{}, BoolTag<true>{});
         }
 
         S1 = wave_sum(S1);

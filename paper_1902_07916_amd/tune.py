@@ -95,7 +95,7 @@ def _bucket_rate(zi, name, D, ev, n_target, N, trials):
 
 
 def rate_table(evals=("fp32", "fp64"), dims=(2, 4, 6, 9, 12, 16), n_target=65536, N=16384, trials=3,
-               tune_path=None):
+               tune_path=None, names=None):
     """Sampling-kernel rate per bucket from HIP-event kernel time, with the
     fraction of the ALU roofline."""
     from paper_1902_07916_amd import Integrator
@@ -104,7 +104,7 @@ def rate_table(evals=("fp32", "fp64"), dims=(2, 4, 6, 9, 12, 16), n_target=65536
     zi = Integrator(arena_bytes=16 << 30, tune_path=tune_path)
     rows = []
     for ev in evals:
-        for name in REGISTRY:
+        for name in (names or REGISTRY):
             for D in dims:
                 if ev == "fp64" and D not in (4, 6, 9):
                     continue
@@ -210,8 +210,8 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=None)
     ap.add_argument("--table", action="store_true", help="print the sampling rate per bucket and exit")
-    ap.add_argument("--dims", default="2-12")
-    ap.add_argument("--integrands", default="genz_osc,genz_ppeak,genz_cpeak,genz_gauss,gauss,sin_sum")
+    ap.add_argument("--dims", default=None, help="default 2-12; with --table 2,4,6,9,12,16")
+    ap.add_argument("--integrands", default=None)
     ap.add_argument("--evals", default="fp32")
     ap.add_argument("--samples", type=int, default=16384, help="points per cube")
     ap.add_argument("--waves", action="store_true",
@@ -222,17 +222,19 @@ def main(argv=None) -> int:
                          "to --out")
     a = ap.parse_args(argv)
     if a.table:
-        rate_table(evals=a.evals.split(","), N=a.samples, tune_path=a.tune_path)
+        rate_table(evals=a.evals.split(","), N=a.samples, tune_path=a.tune_path,
+                   dims=_parse_dims(a.dims) if a.dims else (2, 4, 6, 9, 12, 16),
+                   names=a.integrands.split(",") if a.integrands else None)
         return 0
     if a.blocks:
         if not a.out:
             ap.error("--blocks needs --out")
-        block_sweep(a.out, evals=a.evals.split(","), dims=_parse_dims(a.dims), N=a.samples)
+        block_sweep(a.out, evals=a.evals.split(","), dims=_parse_dims(a.dims or "2-12"), N=a.samples)
         return 0
     if a.waves:
         if not a.out:
             ap.error("--waves needs --out")
-        wave_sweep(a.out, evals=a.evals.split(","), dims=_parse_dims(a.dims), N=a.samples)
+        wave_sweep(a.out, evals=a.evals.split(","), dims=_parse_dims(a.dims or "2-12"), N=a.samples)
         return 0
     if not a.out:
         ap.error("--out is required unless --table")
@@ -240,8 +242,8 @@ def main(argv=None) -> int:
     table = {}
     if os.path.exists(a.out):
         table = json.load(open(a.out))
-    for name in a.integrands.split(","):
-        for D in _parse_dims(a.dims):
+    for name in (a.integrands or "genz_osc,genz_ppeak,genz_cpeak,genz_gauss,gauss,sin_sum").split(","):
+        for D in _parse_dims(a.dims or "2-12"):
             for ev in a.evals.split(","):
                 times = {g: time_bucket(name, D, ev, g, N=a.samples) for g in CANDIDATES}
                 best = min(times, key=times.get)
