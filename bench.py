@@ -158,6 +158,20 @@ def _oracle_cubes(args):
     return n, time.perf_counter() - t0
 
 
+def _oracle_cube_range(args):
+    """Worker of the all-core reduced-size leg: oracle.cube on level-0 cubes
+    first, first + stride, ... below n; returns (cubes, seconds)."""
+    w, first, stride, n = args
+    import oracle
+    p = _oracle_problem(w)
+    t0 = time.perf_counter()
+    k = 0
+    for c in range(first, n, stride):
+        oracle.cube(p, 0, c)
+        k += 1
+    return k, time.perf_counter() - t0
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -227,6 +241,67 @@ def percentile(xs, q):
     f = int(math.floor(k))
     c = min(f + 1, len(xs) - 1)
     return xs[f] + (xs[c] - xs[f]) * (k - f)
+
+
+def run_cpu(a) -> dict:
+    """The oracle at reduced sizes on this host, each beside the GPU doing the
+    same work: the 4-D Gaussian workload whole, the narrow 9-D Gaussian
+    whole at N/16 (both single thread), and level 0 of the 6-D sine at N/16
+    on all cores (cube c to worker c mod P).  Takes a few minutes."""
+    import multiprocessing as mp
+
+    import torch
+
+    import oracle
+    from paper_1902_07916_amd import Integrator, workloads
+    oracle.build()
+    zi = Integrator(arena_bytes=int(a.arena_gib * (1 << 30)))
+
+    def gpu_time(w, reps=3):
+        zi.integrate(**w)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = zi.integrate(**w)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps, r
+
+    out = {"cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    g9 = dict(workloads.narrow_gauss9d(eval="fp64"))
+    g9["samples"] //= 16
+    for name, w in (("gauss4d_whole", workloads.gauss4d(eval="fp64")), ("narrow_gauss9d_n16_whole", g9)):
+        t0 = time.perf_counter()
+        o = oracle.integrate(_oracle_problem(w))
+        cpu_s = time.perf_counter() - t0
+        row = {"cores": 1, "cpu_s": cpu_s, "samples": o.n_samples, "cpu_samples_per_s": o.n_samples / cpu_s,
+               "cpu_integral": o.integral, "cpu_levels": [L.n for L in o.levels]}
+        for ev in ("fp64", "fp32"):
+            dt, r = gpu_time(dict(w, eval=ev))
+            row["gpu_%s_s" % ev] = dt
+            row["gpu_%s_integral" % ev] = r.integral
+            row["gpu_%s_levels" % ev] = r.cubes_per_level[:r.levels_run]
+        row["speedup_gpu_fp32"] = cpu_s / row["gpu_fp32_s"]
+        out[name] = row
+        print("%s: cpu %.2f s, gpu fp64 %.4f s, fp32 %.4f s" % (name, cpu_s, row["gpu_fp64_s"], row["gpu_fp32_s"]),
+              file=sys.stderr, flush=True)
+    w6 = dict(workloads.sin6d(eval="fp64"))
+    w6["samples"] //= 16
+    w6["max_depth"] = 0
+    n = w6["divisions"] ** len(w6["lower"])
+    P = host_cores()
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(P) as pool:
+        res = pool.map(_oracle_cube_range, [(w6, i, P, n) for i in range(P)])
+    cpu_s = time.perf_counter() - t0
+    assert sum(k for k, _ in res) == n
+    samples = n * w6["trials"] * w6["samples"]
+    row = {"cores": P, "cpu_s": cpu_s, "samples": samples, "cpu_samples_per_s": samples / cpu_s}
+    for ev in ("fp64", "fp32"):
+        row["gpu_%s_s" % ev] = gpu_time(dict(w6, eval=ev))[0]
+    row["speedup_gpu_fp32"] = cpu_s / row["gpu_fp32_s"]
+    out["sin6d_n16_level0_all_cores"] = row
+    zi.close()
+    return out
 
 
 def run_batch(a, steps=None, warmup=None) -> dict:
@@ -384,7 +459,7 @@ def main(argv=None) -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="sin6d", choices=sorted(WORKLOADS))
-    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "paper"])
+    ap.add_argument("--mode", default="single", choices=["single", "batch", "serve", "paper", "cpu"])
     ap.add_argument("--no-fp64", action="store_true", help="skip timing the plain FP64 path")
     ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--batch-steps", type=int, default=1,
@@ -416,6 +491,9 @@ def main(argv=None) -> int:
         return 0
     if a.mode == "batch":
         print(json.dumps({"mode": "batch", **run_batch(a)}))
+        return 0
+    if a.mode == "cpu":
+        print(json.dumps({"mode": "cpu", **run_cpu(a)}))
         return 0
     if a.mode == "serve":
         print(json.dumps({"mode": "serve", **run_serve(a)}))

@@ -281,9 +281,12 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
         // SIMD less in several buckets).
         // FP32 evaluation adds a group's 4 values in FP32 (in point order)
         // and the group's sum in FP64: one conversion and one FP64 add per
-        // group instead of per point.
+        // group instead of per point.  At D = 6 and 7 that ran 1-3% slower in
+        // a same-box A/B (the instruction schedule, at the same registers),
+        // so there each value is added in FP64 as it comes.
         constexpr bool kWholeLoop = D < kHalvesMinD && (W <= 5 || (W == 7 && D <= 6));
         constexpr bool kUniformLoop = FP32 && D <= 3;
+        constexpr bool kGroupSum = FP32 && D != 6 && D != 7;
         auto run = [&](auto masked, auto tested) {
             constexpr bool kMasked = decltype(masked)::value;
             for (int j = 0; j < G; ++j) {
@@ -294,7 +297,7 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
                     if (s0 >= N) break;
                     if constexpr (kMasked) nvalid = (int)min((int64_t)4, N - s0);
                 }
-                float gs = 0.0f;
+                [[maybe_unused]] float gs = 0.0f;
                 group_samples<D>((uint32_t)g * (uint32_t)D, c1, c2, c3, k0, k1, [&](int q, const uint32_t* w) {
                     if constexpr (FP32) {
                         float v[D];
@@ -302,7 +305,11 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
                         for (int i = 0; i < D; ++i) v[i] = unit_interval_f32(w[i]);
                         float f = I::f32(cs.p, v);
                         if constexpr (kMasked) f = (q < nvalid) ? f : 0.0f;
-                        gs = q == 0 ? f : gs + f;
+                        if constexpr (kGroupSum) {
+                            gs = q == 0 ? f : gs + f;
+                        } else {
+                            S1 += (double)f;
+                        }
                         if constexpr (KEEP_S2) {
                             const double fd = (double)f;
                             S2 = fma(fd, fd, S2);
@@ -319,7 +326,7 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
                         if constexpr (KEEP_S2) S2 = fma(f, f, S2);
                     }
                 });
-                if constexpr (FP32) S1 += (double)gs;
+                if constexpr (kGroupSum) S1 += (double)gs;
             }
         };
         if constexpr (kWholeLoop && kUniformLoop) {
