@@ -45,12 +45,16 @@ def valu_instructions_per_sample(integrand: str, D: int, eval_: str) -> dict:
     over a wave the first round's product of word 2, its XOR and the second
     round's product of word 0 are scalar work: 18 v_mad_u64_u32 + 19
     v_bitop3_b32 per block.  Mapping: one v_alignbit_b32 per coordinate plus
-    the FMA that places it.  Integrand and the FP64 accumulation of the sum
-    (convert, add) per family; the sum of squares is kept only on traced
+    the FMA that places it.  Integrand per family.  Accumulation: in FP32
+    evaluation a lane's 4 values of a group are added in FP32 (3 adds) and
+    the group's sum converted and added in FP64 (2 instructions), 0.75 FP32
+    and 0.5 FP64 instructions per sample (the kernels at D = 6 and 7 convert
+    and add every value, 2 FP64 instructions, and are held to the same
+    floor); in FP64, one add.  The sum of squares is kept only on traced
     levels and is not counted."""
     rng = D / 4.0 * 37
     if eval_ == "fp32":
-        ints, fp32, fp64, trans = rng + D, float(D), 2.0, 0.0
+        ints, fp32, fp64, trans = rng + D, float(D) + 0.75, 0.5, 0.0
         if integrand in ("sin_sum", "genz_osc"):
             # high part of the cube phase; r - rint(r) (rint, sub), fold
             # a = min(|t|, 1/2 - |t|) (sub, min), a^2, 6 FMA, *a; the sign

@@ -20,7 +20,9 @@
  *   oracle_cube_bounds    pinned: children tile the parent; leaves tile the domain.
  *   oracle_cube_trial     pinned: closed forms (erf, complex exponential, atan,
  *                         inclusion-exclusion, monomials), 2-D Riemann sums.
- *   oracle_threshold      pinned: numpy population std; hand examples.
+ *   oracle_threshold      pinned: numpy population std; hand examples; values
+ *                         whose squared deviations underflow (numpy on
+ *                         values scaled by a power of two).
  *   oracle_set_user       pinned: a user function equal to a registry
  *                         integrand reproduces it bit for bit; closed form.
  *   oracle_integrate      pinned: closed forms within k*stderr, constant
@@ -400,9 +402,34 @@ int oracle_cube_trial(const oracle_problem* p, int level, uint64_t uid, int tria
     return oracle_cube_trial_w(p, level, uid, 0, trial, I_t, S1_out, S2_out, SA_out);
 }
 
+/* Population standard deviation of x[0..n) around mean (Sec. 2.1 uses the
+ * standard deviation of the trial values and of the cubes' deviations):
+ * sqrt(sum (x - mean)^2 / n), serial sum.  Reading: each deviation is scaled
+ * by 2^-e, e the binary exponent of the largest |x - mean| (frexp), before
+ * it is squared, and the root by 2^e after.  Powers of two scale exactly, so
+ * wherever the unscaled squares neither underflow nor overflow this is the
+ * same number bit for bit; where they would (deviations below ~1e-154, as in
+ * the tails of a narrow Gaussian), the deviations are not lost. */
+static double or_pop_std(const double* x, int64_t n, double mean)
+{
+    double dmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double d = fabs(x[i] - mean);
+        if (d > dmax) dmax = d;
+    }
+    int e = 0;
+    if (isfinite(dmax) && dmax > 0.0) (void)frexp(dmax, &e);
+    double ss = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const double d = ldexp(x[i] - mean, -e);
+        ss += d * d;
+    }
+    return ldexp(sqrt(ss / (double)n), e);
+}
+
 /* Mean and standard deviation of the n1 trial values of one sub-domain
- * (Sec. 2.1).  Reading: population std (ddof = 0), two passes, serial sums.
- * I_out (length n1) may be NULL. */
+ * (Sec. 2.1).  Reading: population std (ddof = 0, or_pop_std), two passes,
+ * serial sums.  I_out (length n1) may be NULL. */
 int oracle_cube_w(const oracle_problem* p, int level, uint64_t uid, uint32_t uid_hi, double* I_out, double* m_out,
                   double* s_out, double* SA_out)
 {
@@ -419,10 +446,8 @@ int oracle_cube_w(const oracle_problem* p, int level, uint64_t uid, uint32_t uid
     double sum = 0.0;
     for (int t = 0; t < n1; ++t) sum += I[t];
     double m = sum / (double)n1;
-    double ss = 0.0;
-    for (int t = 0; t < n1; ++t) ss += (I[t] - m) * (I[t] - m);
     *m_out = m;
-    *s_out = sqrt(ss / (double)n1);
+    *s_out = or_pop_std(I, n1, m);
     if (SA_out) {
         double lo[OR_MAX_DIM], h[OR_MAX_DIM], vol;
         oracle_cube_bounds_w(p, level, uid, uid_hi, lo, h, &vol);
@@ -441,15 +466,14 @@ int oracle_cube(const oracle_problem* p, int level, uint64_t uid, double* I_out,
 /* Threshold over one level's standard deviations (Sec. 2.1: the threshold is
  * set from the mean and the standard deviation of the k standard deviations;
  * Sec. 3 applies it as a five-sigma cut).  Reading: thr = mean(s) +
- * sigma_mult * std(s), population std, two passes, serial sums. */
+ * sigma_mult * std(s), population std (or_pop_std), two passes, serial
+ * sums. */
 double oracle_threshold(const double* s, int64_t n, double sigma_mult, double* mu_out, double* sd_out)
 {
     double sum = 0.0;
     for (int64_t c = 0; c < n; ++c) sum += s[c];
     double mu = sum / (double)n;
-    double ss = 0.0;
-    for (int64_t c = 0; c < n; ++c) ss += (s[c] - mu) * (s[c] - mu);
-    double sd = sqrt(ss / (double)n);
+    double sd = or_pop_std(s, n, mu);
     if (mu_out) *mu_out = mu;
     if (sd_out) *sd_out = sd;
     return mu + sigma_mult * sd;

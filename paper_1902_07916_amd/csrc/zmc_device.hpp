@@ -67,11 +67,25 @@ struct alignas(16) BSeg {
 // Per-tile partial reductions of the per-cube kernels.
 struct alignas(16) TileRec {
     double sum_s, sum_sq;
+    double s_min, s_max; // extremes of the tile's s (for the scale of the std)
     double accM, accS2, selM, selS2;
     double min_margin;
     int64_t n_sel, sel_prefix;
     int32_t nonfinite, pad;
 };
+
+// Population standard deviations are computed with every deviation scaled
+// by 2^-e before it is squared and the root scaled by 2^e after, e the
+// binary exponent of the largest |deviation| (frexp).  Powers of two scale
+// exactly: wherever the unscaled squares neither underflow nor overflow the
+// result is the same bit for bit, and deviations below ~1e-154 (the tails of
+// a narrow Gaussian) are not lost to underflow.
+__device__ __forceinline__ int std_scale_exp(double dmax)
+{
+    int e = 0;
+    if (isfinite(dmax) && dmax > 0.0) (void)frexp(dmax, &e);
+    return e;
+}
 
 enum Decision : int32_t { kSplit = 0, kDone = 1, kTruncated = 2, kRtolMet = 3 };
 
@@ -102,6 +116,7 @@ constexpr int32_t kRangeLost = 1;
 // Per-segment outcome of one level, read back by the host after every level.
 struct alignas(16) SegStats {
     double mu, sd, thr, min_margin;
+    double s_min, s_max; // extremes of the segment's s
     double accM, accS2, selM, selS2;
     double totM, totS2; // running totals of the integral after this level
     int64_t n_sel;

@@ -44,6 +44,13 @@ __device__ __forceinline__ double wave_min(double v)
     return v;
 }
 
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
 __device__ __forceinline__ int64_t wave_sum_i(int64_t v)
 {
 #pragma unroll
@@ -73,6 +80,18 @@ __device__ double block_min(double v, double* sh)
     double t = sh[0];
 #pragma unroll
     for (int w = 1; w < kWaves; ++w) t = fmin(t, sh[w]);
+    return t;
+}
+
+__device__ double block_max(double v, double* sh)
+{
+    v = wave_max(v);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double t = sh[0];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) t = fmax(t, sh[w]);
     return t;
 }
 
@@ -189,10 +208,28 @@ __device__ void seg_mean(const LevelArgs& a, int si)
 {
     __shared__ double sh[kWaves];
     const Segment& sg = a.segs[si];
-    double v = 0.0;
-    for (int64_t t = threadIdx.x; t < sg.n_tiles; t += kLevelThreads) v += a.tiles[sg.tile_base + t].sum_s;
+    double v = 0.0, lo = DBL_MAX, hi = -DBL_MAX;
+    for (int64_t t = threadIdx.x; t < sg.n_tiles; t += kLevelThreads) {
+        const TileRec& T = a.tiles[sg.tile_base + t];
+        v += T.sum_s;
+        lo = fmin(lo, T.s_min);
+        hi = fmax(hi, T.s_max);
+    }
     const double tot = block_sum(v, sh);
-    if (threadIdx.x == 0) a.stats[si].mu = tot / (double)sg.n_cubes;
+    lo = block_min(lo, sh);
+    hi = block_max(hi, sh);
+    if (threadIdx.x == 0) {
+        a.stats[si].mu = tot / (double)sg.n_cubes;
+        a.stats[si].s_min = lo;
+        a.stats[si].s_max = hi;
+    }
+}
+
+// The scale exponent of the threshold's std: the largest |s - mu| is at the
+// smallest or the largest s (rounding is monotonic).
+__device__ __forceinline__ int thr_scale_exp(double mu, double lo, double hi)
+{
+    return std_scale_exp(fmax(fabs(hi - mu), fabs(lo - mu)));
 }
 
 __device__ void seg_thr(const LevelArgs& a, int si)
@@ -203,13 +240,16 @@ __device__ void seg_thr(const LevelArgs& a, int si)
     for (int64_t t = threadIdx.x; t < sg.n_tiles; t += kLevelThreads) v += a.tiles[sg.tile_base + t].sum_sq;
     const double tot = block_sum(v, sh);
     if (threadIdx.x == 0) {
-        const double sd = sqrt(tot / (double)sg.n_cubes);
+        const SegStats& S = a.stats[si];
+        const double sd = ldexp(sqrt(tot / (double)sg.n_cubes), thr_scale_exp(S.mu, S.s_min, S.s_max));
         a.stats[si].sd = sd;
         a.stats[si].thr = a.stats[si].mu + a.slots[sg.slot].sigma_mult * sd;
     }
 }
 
 __device__ void seg_decide(const LevelArgs& a, int si);
+__device__ void decide_write(const LevelArgs& a, int si, double accM, double accS2, double selM, double selS2,
+                             double margin, int64_t nsel, int bad);
 
 // ---- finalize: per cube I_t = V * S1_t / N, m = mean I_t, s = std I_t ------
 // The partial sums of 256 consecutive cubes are contiguous ([cube][trial *
@@ -218,7 +258,14 @@ __device__ void seg_decide(const LevelArgs& a, int si);
 // there.  Larger rows (many trials or chunks) are read from memory directly.
 constexpr int kStage = 2560; // 40 KiB of (S1, S2) pairs
 
-__device__ void finalize_tile(const LevelArgs& a, int64_t tile, int si)
+// KEEP: also leave each thread's cubes' m and s in m_r / s_r (pass j at
+// index j), for the one-block level path.
+// KEEP also returns the tile's sum of s, non-finite flag and extremes of s
+// (every thread).
+template <bool KEEP = false>
+__device__ void finalize_tile(const LevelArgs& a, int64_t tile, int si, double* m_r = nullptr,
+                              double* s_r = nullptr, double* tot_s = nullptr, int* any_bad_out = nullptr,
+                              double* s_ext = nullptr)
 {
     __shared__ double sh[kWaves];
     __shared__ double2 stage[kStage];
@@ -230,8 +277,9 @@ __device__ void finalize_tile(const LevelArgs& a, int64_t tile, int si)
     const double V = cube_volume(sd, D, sg.level);
     const double N = (double)sd.samples;
     const int64_t first = (tile - sg.tile_base) * kTileCubes;
-    double sum_s = 0.0;
+    double sum_s = 0.0, s_lo = DBL_MAX, s_hi = -DBL_MAX;
     int bad = 0;
+#pragma unroll
     for (int j = 0; j < kPerThread; ++j) {
         const int64_t c0 = first + (int64_t)j * kLevelThreads; // first cube of this pass
         if (c0 >= sg.n_cubes) break;                            // uniform over the block
@@ -264,24 +312,48 @@ __device__ void finalize_tile(const LevelArgs& a, int64_t tile, int si)
             sum += V * (S1 / N);
         }
         const double m = sum / (double)n1;
+        double dmax = 0.0;
+        for (int t = 0; t < n1; ++t) {
+            double S1 = 0.0;
+            for (int ch = 0; ch < nch; ++ch) S1 += P[t * nch + ch].x;
+            const double d = fabs(V * (S1 / N) - m);
+            if (d > dmax) dmax = d;
+        }
+        const int e = std_scale_exp(dmax);
         double ss = 0.0;
         for (int t = 0; t < n1; ++t) {
             double S1 = 0.0;
             for (int ch = 0; ch < nch; ++ch) S1 += P[t * nch + ch].x;
-            const double d = V * (S1 / N) - m;
+            const double d = ldexp(V * (S1 / N) - m, -e);
             ss += d * d;
         }
-        const double s = sqrt(ss / (double)n1);
+        const double s = ldexp(sqrt(ss / (double)n1), e);
         a.m[c] = m;
         a.s[c] = s;
+        if constexpr (KEEP) {
+            m_r[j] = m;
+            s_r[j] = s;
+        }
         sum_s += s;
+        s_lo = fmin(s_lo, s);
+        s_hi = fmax(s_hi, s);
         bad |= !(isfinite(m) && isfinite(s));
     }
     const double tot = block_sum(sum_s, sh);
+    const double lo = block_min(s_lo, sh);
+    const double hi = block_max(s_hi, sh);
     const int any_bad = __syncthreads_or(bad);
     if (threadIdx.x == 0) {
         a.tiles[tile].sum_s = tot;
+        a.tiles[tile].s_min = lo;
+        a.tiles[tile].s_max = hi;
         a.tiles[tile].nonfinite = any_bad;
+    }
+    if constexpr (KEEP) {
+        *tot_s = tot;
+        *any_bad_out = any_bad;
+        s_ext[0] = lo;
+        s_ext[1] = hi;
     }
 }
 
@@ -301,12 +373,13 @@ __device__ void sqdev_tile(const LevelArgs& a, int64_t tile, int si)
     __shared__ double sh[kWaves];
     const Segment& sg = a.segs[si];
     const double mu = a.stats[si].mu;
+    const int e = thr_scale_exp(mu, a.stats[si].s_min, a.stats[si].s_max);
     const int64_t first = (tile - sg.tile_base) * kTileCubes;
     double acc = 0.0;
     for (int j = 0; j < kPerThread; ++j) {
         const int64_t cl = first + threadIdx.x + (int64_t)j * kLevelThreads;
         if (cl >= sg.n_cubes) break;
-        const double d = a.s[sg.cube_base + cl] - mu;
+        const double d = ldexp(a.s[sg.cube_base + cl] - mu, -e);
         acc += d * d;
     }
     const double tot = block_sum(acc, sh);
@@ -365,12 +438,15 @@ __global__ __launch_bounds__(kLevelThreads) void group_thr_kernel(const LevelArg
         double v = 0.0;
         for (int64_t j = lane; j < gs; j += 64) v += s[j];
         const double mu = wave_sum(v) / (double)gs;
+        double dmax = 0.0;
+        for (int64_t j = lane; j < gs; j += 64) dmax = fmax(dmax, fabs(s[j] - mu));
+        const int e = std_scale_exp(wave_max(dmax));
         double q = 0.0;
         for (int64_t j = lane; j < gs; j += 64) {
-            const double d = s[j] - mu;
+            const double d = ldexp(s[j] - mu, -e);
             q += d * d;
         }
-        const double sd = sqrt(wave_sum(q) / (double)gs);
+        const double sd = ldexp(sqrt(wave_sum(q) / (double)gs), e);
         if (lane == 0) a.gthr[g] = mu + a.slots[sg.slot].sigma_mult * sd;
     }
 }
@@ -479,7 +555,17 @@ __device__ void seg_decide(const LevelArgs& a, int si)
         carry += chunk;
     }
 
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0) decide_write(a, si, accM, accS2, selM, selS2, margin, nsel, bad);
+}
+
+// The segment's outcome from its totals (thread 0): stop rules, running
+// totals, the record in device memory and in the mapped host buffer.
+__device__ void decide_write(const LevelArgs& a, int si, double accM, double accS2, double selM, double selS2,
+                             double margin, int64_t nsel, int bad)
+{
+    const Segment& sg = a.segs[si];
+    const SlotDesc& sd = a.slots[sg.slot];
+    {
         SegStats& S = a.stats[si];
         const double2 prev = a.prev_tot[si];
         if (!sg.need_thr || sg.group_size) {
@@ -526,29 +612,81 @@ __global__ __launch_bounds__(kLevelThreads) void seg_decide_kernel(const LevelAr
 // ---- a whole small level in one launch ----------------------------------------
 // When every segment of the level is one tile (at most 1024 cubes) and no
 // segment forms per-parent thresholds, one block per segment runs finalize,
-// the mean of s, the threshold and the decision in sequence.  With one tile
-// per segment each per-segment reduction of the multi-launch path reduces a
-// single tile record, so this is the same arithmetic in the same order and
-// the results are bitwise those of the three launches.
+// the mean of s, the threshold, the selection and the decision, with each
+// thread's m and s kept in registers between the steps and the reductions in
+// LDS.  With one tile per segment each per-segment reduction of the
+// multi-launch path reduces a single tile record (the other threads add
+// zeros), so this is the same arithmetic in the same order and the results
+// are bitwise those of the multi-launch path.
 __global__ __launch_bounds__(kLevelThreads) void level_small_kernel(const LevelArgs a)
 {
+    __shared__ double sh[kWaves];
     const int si = blockIdx.x;
     const Segment& sg = a.segs[si];
     const int64_t tile = sg.tile_base;
-    const bool thr = sg.need_thr && !sg.group_size;
-    finalize_tile(a, tile, si);
-    __syncthreads();
-    if (thr) {
-        seg_mean(a, si);
-        __syncthreads();
-        sqdev_tile(a, tile, si);
-        __syncthreads();
-        seg_thr(a, si);
-        __syncthreads();
+    const bool thr_on = sg.need_thr != 0;
+    double m_r[kPerThread], s_r[kPerThread];
+    double tot_s = 0.0, s_ext[2] = {0.0, 0.0};
+    int bad = 0;
+    finalize_tile<true>(a, tile, si, m_r, s_r, &tot_s, &bad, s_ext);
+    const int64_t n = sg.n_cubes;
+    double mu = 0.0, sdv = 0.0, thr = 0.0, tot_sq = 0.0;
+    if (thr_on) {
+        mu = tot_s / (double)n;
+        const int e = thr_scale_exp(mu, s_ext[0], s_ext[1]);
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < kPerThread; ++j) {
+            const int64_t cl = threadIdx.x + (int64_t)j * kLevelThreads;
+            if (cl < n) {
+                const double d = ldexp(s_r[j] - mu, -e);
+                acc += d * d;
+            }
+        }
+        tot_sq = block_sum(acc, sh);
+        sdv = ldexp(sqrt(tot_sq / (double)n), e);
+        thr = mu + a.slots[sg.slot].sigma_mult * sdv;
     }
-    select_tile(a, tile, si);
-    __syncthreads();
-    seg_decide(a, si);
+    double accM = 0.0, accS2 = 0.0, selM = 0.0, selS2 = 0.0, margin = DBL_MAX;
+    int64_t nsel = 0;
+#pragma unroll
+    for (int j = 0; j < kPerThread; ++j) {
+        const int64_t cl = threadIdx.x + (int64_t)j * kLevelThreads;
+        if (cl >= n) break;
+        const int64_t c = sg.cube_base + cl;
+        const double m = m_r[j], s = s_r[j];
+        const bool sel = thr_on && (s > thr);
+        a.sel[c] = sel ? 1 : 0;
+        if (sel) {
+            selM += m;
+            selS2 += s * s;
+            ++nsel;
+        } else {
+            accM += m;
+            accS2 += s * s;
+        }
+        if (thr_on && thr > 0.0) margin = fmin(margin, fabs(s - thr) / thr);
+    }
+    const SelTotals tot = block_reduce_sel(SelTotals{accM, accS2, selM, selS2, margin, nsel});
+    if (threadIdx.x == 0) {
+        TileRec& T = a.tiles[tile];
+        T.sum_sq = tot_sq;
+        T.accM = tot.accM;
+        T.accS2 = tot.accS2;
+        T.selM = tot.selM;
+        T.selS2 = tot.selS2;
+        T.min_margin = tot.margin;
+        T.n_sel = tot.nsel;
+        T.sel_prefix = 0;
+        if (thr_on) {
+            a.stats[si].mu = mu;
+            a.stats[si].s_min = s_ext[0];
+            a.stats[si].s_max = s_ext[1];
+            a.stats[si].sd = sdv;
+            a.stats[si].thr = thr;
+        }
+        decide_write(a, si, tot.accM, tot.accS2, tot.selM, tot.selS2, tot.margin, tot.nsel, bad);
+    }
 }
 
 // ---- spawn: children of the selected cubes, in list order ------------------

@@ -106,3 +106,21 @@ def test_paper_f2_fp32_reports_range_loss(zi, name):
                                                            r32.flags), flush=True)
     assert r64.status == 0 and r64.selected_per_level[0] >= 1 and not r64.flags & F_FP32_RANGE
     assert r32.status == 0 and r32.flags & F_FP32_RANGE
+
+
+def test_paper_12d_tail_std_keeps_the_peak(zi, orc):
+    """The 12-D run of Table 4 under the literal split, seed 2: the centre
+    root cube's trial values lie between 1e-240 and 1e-186, so their squared
+    deviations fall below FP64's range and an unscaled std is 0, which would
+    leave the peak's cube unselected.  With the std's power-of-two scaling
+    the cube is selected at every level and the estimate is near 1."""
+    from paper_1902_07916_amd import workloads as W
+    w = W.paper_run("f2_12d_ray", eval="fp64", seed=2, split=3)
+    print("paper run f2_12d_ray split=3 fp64 seed 2 at N=%d" % w["samples"], flush=True)
+    r = zi.integrate(**w, trace=True, trace_capacity=3 << 20)
+    assert r.status == 0 and r.levels_run == w["max_depth"] + 1
+    assert all(n >= 1 for n in r.selected_per_level[:w["max_depth"]])
+    assert abs(r.integral - 1.0) < 0.01
+    check_levels_sampled(orc, w, r, 4, 1e-12)
+    print("  levels %s, selected %s, integral %.6g +- %.3g" % (r.cubes_per_level, r.selected_per_level,
+                                                             r.integral, r.stderr))

@@ -142,3 +142,36 @@ def test_nonfinite_integrand_fails_run(orc):
     p = orc.problem(orc.CONST, 2, 0.0, 1.0, 2, 8, 3, 1, 1.0, 1, params=[float("nan")])
     r = orc.integrate(p)
     assert r.status == orc.ENONFINITE
+
+
+def test_std_of_tiny_values(orc):
+    # deviations near 1e-200: their squares lie below FP64's range, so an
+    # unscaled sum of squares is 0; numpy on the values scaled by 2^700
+    # (exact) gives the reference
+    s = np.array([1.0, 2.0, 4.0, 3.5, 0.25]) * 1e-200
+    thr, mu, sd = orc.threshold(s, 2.0)
+    ref = np.std(s * 2.0 ** 700) * 2.0 ** -700
+    assert sd > 0 and sd == pytest.approx(ref, rel=1e-15)
+    assert mu == pytest.approx(np.mean(s), rel=1e-15)
+    assert thr == pytest.approx(mu + 2.0 * ref, rel=1e-15)
+    # the scaling is exact: ordinary values give the unscaled formula's bits
+    x = np.random.default_rng(5).lognormal(size=257)
+    _, mu2, sd2 = orc.threshold(x, 1.0)
+    assert sd2 == math.sqrt(sum((v - mu2) ** 2 for v in x) / len(x))
+
+
+def test_cube_std_of_tiny_trials(orc):
+    # the 12-D normalised Gaussian (sigma 0.01, 3 cells per axis, 10^4
+    # points, 5 trials), seed 2: the centre root cube's trial values are
+    # 1e-240 .. 1e-186, whose squared deviations underflow; its std is that
+    # of the values scaled by a power of two
+    import common
+    from paper_1902_07916_amd import workloads
+    D = 12
+    p = common.oracle_problem(orc, workloads.paper_run("f2_12d_ray", eval="fp64", seed=2, split=3))
+    uid = (3 ** D - 1) // 2
+    st, I, m, s, sa = orc.cube(p, 0, uid)
+    assert st == 0 and I.max() > 0
+    ref = np.std(I * 2.0 ** 600) * 2.0 ** -600
+    assert s > 0 and s == pytest.approx(ref, rel=1e-14)
+    assert m == pytest.approx(np.mean(I * 2.0 ** 600) * 2.0 ** -600, rel=1e-14)
