@@ -110,30 +110,45 @@ WORKLOADS = {
 # level kernels' arguments and launchers in zmc_kernels.hpp do not enter it).
 KERNEL_SOURCES = ("paper_1902_07916_amd/build.py", "paper_1902_07916_amd/csrc/zmc_sample.hip",
                   "paper_1902_07916_amd/csrc/zmc_sample_core.hpp", "paper_1902_07916_amd/csrc/zmc_integrands.hpp",
-                  "paper_1902_07916_amd/csrc/zmc_device.hpp", "paper_1902_07916_amd/csrc/zmc_tune_gfx950.json")
+                  "paper_1902_07916_amd/csrc/zmc_device.hpp")
+TUNE_TABLE = "paper_1902_07916_amd/csrc/zmc_tune_gfx950.json"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sample_kernel.json")
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(bucket: str) -> str:
+    """Hash of what decides one sampling bucket's machine code and launch:
+    the kernel sources and the tuning table's entries for that bucket
+    ("integrand:dim:eval")."""
     import hashlib
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(ROOT, TUNE_TABLE)) as fh:
+        table = json.load(fh)
+    h.update(json.dumps({k: v for k, v in sorted(table.items()) if k.startswith(bucket + ":")}).encode())
     return h.hexdigest()[:16]
+
+
+def workload_bucket(workload: str) -> str:
+    """The (integrand, dim, eval) bucket of a workload's FP32 sampling kernel."""
+    from paper_1902_07916_amd import INTEGRANDS, workloads
+    gen, integrand, _ = WORKLOADS[workload]
+    w = getattr(workloads, gen)(eval="fp32")
+    return "%d:%d:1" % (INTEGRANDS[integrand], len(w["lower"]))
 
 
 def measured_traffic(workload: str):
     """HBM bytes per launch of the sampling kernel from the committed
-    FETCH_SIZE / WRITE_SIZE runs, or None when the kernel sources changed
-    since those counters were taken."""
+    FETCH_SIZE / WRITE_SIZE runs, or None when the kernel sources or the
+    bucket's tuning entries changed since those counters were taken."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
     e = t.get(workload)
-    if not e or e.get("source_hash") != kernel_source_hash():
+    if not e or e.get("source_hash") != kernel_source_hash(workload_bucket(workload)):
         return None
     return e["bytes_per_launch"]
 
