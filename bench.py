@@ -48,9 +48,7 @@ def valu_instructions_per_sample(integrand: str, D: int, eval_: str) -> dict:
     the FMA that places it.  Integrand per family.  Accumulation: in FP32
     evaluation a lane's 4 values of a group are added in FP32 (3 adds) and
     the group's sum converted and added in FP64 (2 instructions), 0.75 FP32
-    and 0.5 FP64 instructions per sample (the kernels at D = 6 and 7 convert
-    and add every value, 2 FP64 instructions, and are held to the same
-    floor); in FP64, one add.  The sum of squares is kept only on traced
+    and 0.5 FP64 instructions per sample; in FP64, one add.  The sum of squares is kept only on traced
     levels and is not counted."""
     rng = D / 4.0 * 37
     if eval_ == "fp32":

@@ -279,14 +279,15 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
         // test: a wave-uniform trip count.  From D = 4 on, and in FP64, that
         // loop took more registers than it saved instructions (one wave per
         // SIMD less in several buckets).
-        // FP32 evaluation adds a group's 4 values in FP32 (in point order)
-        // and the group's sum in FP64: one conversion and one FP64 add per
-        // group instead of per point.  At D = 6 and 7 that ran 1-3% slower in
-        // a same-box A/B (the instruction schedule, at the same registers),
-        // so there each value is added in FP64 as it comes.
+        // FP32 evaluation adds a group's 4 values in FP32 and the group's sum
+        // in FP64: one conversion and one FP64 add per group instead of per
+        // point.  The 4 values are added in point order, except at D = 6 and
+        // 7, where (v0 + v1) + (v2 + v3) ran 1-2.4% faster than both the
+        // point-order sum and per-value FP64 adds in a same-box A/B (and
+        // 0.5-3.7% slower at the other D).
         constexpr bool kWholeLoop = D < kHalvesMinD && (W <= 5 || (W == 7 && D <= 6));
         constexpr bool kUniformLoop = FP32 && D <= 3;
-        constexpr bool kGroupSum = FP32 && D != 6 && D != 7;
+        constexpr bool kPairSum = D == 6 || D == 7;
         auto run = [&](auto masked, auto tested) {
             constexpr bool kMasked = decltype(masked)::value;
             for (int j = 0; j < G; ++j) {
@@ -297,7 +298,7 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
                     if (s0 >= N) break;
                     if constexpr (kMasked) nvalid = (int)min((int64_t)4, N - s0);
                 }
-                [[maybe_unused]] float gs = 0.0f;
+                [[maybe_unused]] float gs = 0.0f, gb = 0.0f;
                 group_samples<D>((uint32_t)g * (uint32_t)D, c1, c2, c3, k0, k1, [&](int q, const uint32_t* w) {
                     if constexpr (FP32) {
                         float v[D];
@@ -305,10 +306,13 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
                         for (int i = 0; i < D; ++i) v[i] = unit_interval_f32(w[i]);
                         float f = I::f32(cs.p, v);
                         if constexpr (kMasked) f = (q < nvalid) ? f : 0.0f;
-                        if constexpr (kGroupSum) {
-                            gs = q == 0 ? f : gs + f;
+                        if constexpr (kPairSum) {
+                            if (q == 0) gs = f;
+                            else if (q == 1) gs = gs + f;
+                            else if (q == 2) gb = f;
+                            else gb = gb + f;
                         } else {
-                            S1 += (double)f;
+                            gs = q == 0 ? f : gs + f;
                         }
                         if constexpr (KEEP_S2) {
                             const double fd = (double)f;
@@ -326,7 +330,7 @@ __device__ __forceinline__ void sample_units(const SampleArgs& a)
                         if constexpr (KEEP_S2) S2 = fma(f, f, S2);
                     }
                 });
-                if constexpr (kGroupSum) S1 += (double)gs;
+                if constexpr (FP32) S1 += (double)(kPairSum ? gs + gb : gs);
             }
         };
         if constexpr (kWholeLoop && kUniformLoop) {
