@@ -182,3 +182,19 @@ def test_tree_through_wide_ids(zi, orc, eval_):
     assert r.levels_run == 12
     assert r.trace[10]["uid_hi"].max() > 0 and r.trace[11]["uid_hi"].max() > 0
     _compare_tree(orc, w, r, EPS64 if eval_ == "fp64" else EPS32, 1e-6 if eval_ == "fp64" else 1e-4)
+
+
+def test_bway_tree_through_wide_ids(zi, orc):
+    """Ids past 64 bits under a b-way split (b = 64, 4096 children per
+    cube): a very narrow 2-D product peak on 8 x 8 roots, split to level 5
+    (6 root bits + 12 per split), whose last level holds ids above 2^64 (the
+    decode divides a 128-bit id by 4096 per level).  FP64 evaluation: in
+    FP32 the peak's values at the root level lie below FP32's range.  The
+    whole tree against the oracle, id lists bit-exact."""
+    w = dict(integrand=3, params=[1e11, 1e11, 0.3141592, 0.2718281], lower=[0.0, 0.0], upper=[1.0, 1.0],
+             divisions=8, samples=64, trials=2, max_depth=5, sigma_mult=3.0, seed=5, split=64,
+             max_cubes_per_level=1 << 14, eval="fp64")
+    r = zi.integrate(**w, trace=True)
+    assert r.levels_run == 6 and not r.flags & 1
+    assert r.trace[5]["uid_hi"].max() > 0
+    _compare_tree(orc, w, r, EPS64, 1e-6)
