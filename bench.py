@@ -111,6 +111,7 @@ KERNEL_SOURCES = ("paper_1902_07916_amd/build.py", "paper_1902_07916_amd/csrc/zm
                   "paper_1902_07916_amd/csrc/zmc_device.hpp")
 TUNE_TABLE = "paper_1902_07916_amd/csrc/zmc_tune_gfx950.json"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sample_kernel.json")
+ISSUE_FILE = os.path.join(ROOT, "profiles", "issue_sample_kernel.json")
 
 
 def kernel_source_hash(bucket: str) -> str:
@@ -149,6 +150,24 @@ def measured_traffic(workload: str):
     if not e or e.get("source_hash") != kernel_source_hash(workload_bucket(workload)):
         return None
     return e["bytes_per_launch"]
+
+
+def measured_issue(workload: str):
+    """The sampling kernel's measured VALU issue utilisation from the
+    committed rocprofv3 counter run (SQ_INSTS_VALU, SQ_ACTIVE_INST_VALU2,
+    GRBM_GUI_ACTIVE): the fraction of SIMD quad-cycles issuing at least one
+    VALU instruction, of those issuing two, and instructions per quad-cycle;
+    None when the kernel sources or the bucket's tuning entries changed
+    since."""
+    try:
+        with open(ISSUE_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = t.get(workload)
+    if not e or e.get("source_hash") != kernel_source_hash(workload_bucket(workload)):
+        return None
+    return {k: e[k] for k in ("valu_busy", "dual_issue", "valu_per_quad_cycle")}
 
 
 def _oracle_problem(w: dict):
@@ -551,7 +570,8 @@ def main(argv=None) -> int:
                 "instructions_per_sample": rl["instructions_per_sample"], "kernel_samples_per_s": k_rate,
                 "roofline_samples_per_s": rl["roofline_samples_per_s"],
                 "int_issue_frac": rl["int_issue_frac"], "int_bound_samples_per_s": rl["int_bound_samples_per_s"],
-                "fp32_flop_frac": k_rate * rl["instructions_per_sample"]["fp32_flops"] / FP32_PEAK_FLOPS}
+                "fp32_flop_frac": k_rate * rl["instructions_per_sample"]["fp32_flops"] / FP32_PEAK_FLOPS,
+                "measured_issue": measured_issue(a.workload)}
 
     out = {"metric": "integrand samples/sec + % FP32 VALU peak vs plain FP64; p50/p99 latency at QPS",
            "value": value, "unit": "samples/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
