@@ -18,7 +18,11 @@
  *     hi32(uid)), lane n & 3, where a cube id has up to 84 bits, uid holding
  *     bits 0..63 and uid_hi bits 64..83; the word w maps to
  *     u = (2*(w >> 9) + 1) * 2^-24 and x_i = fma(h_i, u, lo_i).
- *  3. Per cube: m = mean of the I_t, s = population std of the I_t.
+ *  3. Per cube: m = mean of the I_t, s = population std of the I_t.  Every
+ *     population std scales the deviations by 2^-e before squaring and the
+ *     root by 2^e after (e the binary exponent of the largest deviation):
+ *     the same number where the plain squares neither underflow nor
+ *     overflow, and no deviation lost where they would.
  *  4. Per level and per integral: thr = mean(s) + sigma_mult * std(s)
  *     (population std); a cube with s > thr is split (unless the level is
  *     max_depth), all other cubes are accepted with their m.  With
