@@ -58,7 +58,7 @@ U64 = 2.0 ** -53
 FP32_TRIAL_TOL = 2e-5
 
 
-# Absolute floor of |ds| from squares in the subnormal range (see compare_tree).
+# Absolute floor of |ds| for values near the subnormal range (see compare_tree).
 S_FLOOR = 2.0 ** -532
 
 
@@ -183,9 +183,13 @@ def compare_tree(orc, w, r, eps, tol, report=None):
         dm = np.abs(np.asarray(Lg["m"]) - Lo.m)
         ds = np.abs(np.asarray(Lg["s"]) - Lo.s)
         assert np.all(dm <= dI + slack), "level %d m" % l
-        # s = sqrt(sum (I_t - m)^2 / n1): squares below the normal range are
-        # rounded to multiples of 2^-1074, so s^2 carries an absolute error up
-        # to n1 2^-1074 on each side and s one of sqrt(2 n1 2^-1074) < 2^-532
+        # s = sqrt(sum (I_t - m)^2 / n1), the deviations scaled by a power of
+        # two first, so their squares do not underflow; trial values and
+        # deviations below the normal range still carry absolute roundings of
+        # 2^-1074, which the relative slack does not cover.  S_FLOOR bounds
+        # them generously: it is the bound for unscaled squares, whose
+        # rounding to multiples of 2^-1074 gives s an absolute error of at
+        # most sqrt(2 n1 2^-1074) < 2^-532.
         assert np.all(ds <= dI + slack + S_FLOOR), "level %d s" % l
         with np.errstate(divide="ignore", invalid="ignore"):
             stats["ds"] = max(stats["ds"], float(np.nanmax(np.where(dI + slack + S_FLOOR > 0,
