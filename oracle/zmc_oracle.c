@@ -32,8 +32,10 @@
  *                         (refined, truncated and rtol-stopped trees), the
  *                         closed forms of the integral of |sin| (1-D) and
  *                         |sin(x + y)| (2-D) where it changes sign.
- *   exact tree shape at the large 6-D / 9-D workloads: parity unpinned beyond
- *   self-consistency (nothing external fixes it).
+ *   the exact tree of the large 6-D / 9-D workloads has no external value of
+ *   its own: it is the composition of the steps pinned above (per-cube
+ *   estimates, threshold, strict selection, children), each pinned at sizes
+ *   where an independent value exists.
  */
 #include <math.h>
 #include <stdint.h>
