@@ -208,6 +208,20 @@ def _oracle_cube_range(args):
     return k, time.perf_counter() - t0
 
 
+def _oracle_whole(w):
+    """Worker of the batch-subset leg: one integral's whole tree with the
+    oracle; returns (samples, integral, seconds)."""
+    import oracle
+    t0 = time.perf_counter()
+    o = oracle.integrate(_oracle_problem(w))
+    return o.n_samples, o.integral, time.perf_counter() - t0
+
+
+def _oracle_whole_i(args):
+    i, w = args
+    return i, _oracle_whole(w)
+
+
 def cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -282,16 +296,18 @@ def percentile(xs, q):
 def run_cpu(a) -> dict:
     """The oracle at reduced sizes on this host, each beside the GPU doing the
     same work: the 4-D Gaussian workload whole, the narrow 9-D Gaussian
-    whole at N/16 (both single thread), and level 0 of the 6-D sine at N/16
-    on all cores (cube c to worker c mod P).  Takes a few minutes."""
+    whole at N/16 (both single thread), level 0 of the 6-D sine at N/16 on
+    all cores (cube c to worker c mod P), and every 16th integral of the
+    Genz batch, whole trees at N/16, on all cores (one integral per task).
+    Takes a few minutes."""
     import multiprocessing as mp
 
     import torch
 
     import oracle
-    from paper_1902_07916_amd import Integrator, workloads
+    from paper_1902_07916_amd import Integrator, request_from_dict, workloads
     oracle.build()
-    zi = Integrator(arena_bytes=int(a.arena_gib * (1 << 30)))
+    zi = Integrator(arena_bytes=int(a.arena_gib * (1 << 30)), max_slots=1024)
 
     def gpu_time(w, reps=3):
         zi.integrate(**w)
@@ -336,6 +352,37 @@ def run_cpu(a) -> dict:
         row["gpu_%s_s" % ev] = gpu_time(dict(w6, eval=ev))[0]
     row["speedup_gpu_fp32"] = cpu_s / row["gpu_fp32_s"]
     out["sin6d_n16_level0_all_cores"] = row
+    # every 16th integral of the batch at N/16: integrals are independent, so
+    # a subset's results do not depend on the rest of the batch
+    sub = workloads.genz_batch(n=a.batch_n, max_cubes_per_level=a.batch_cap, samples=4096 // 16)[::16]
+    t0 = time.perf_counter()
+    res = [None] * len(sub)
+    with mp.get_context("spawn").Pool(P) as pool:
+        for k, (i, r) in enumerate(pool.imap_unordered(_oracle_whole_i, list(enumerate(sub)))):
+            res[i] = r
+            if k % 32 == 31:
+                print("batch subset: %d of %d integrals done on the CPU, %.0f s" % (
+                    k + 1, len(sub), time.perf_counter() - t0), file=sys.stderr, flush=True)
+    cpu_s = time.perf_counter() - t0
+    samples = sum(r[0] for r in res)
+    row = {"cores": P, "integrals": len(sub), "cpu_s": cpu_s, "samples": samples,
+           "cpu_samples_per_s": samples / cpu_s, "cpu_integrals_per_s": len(sub) / cpu_s,
+           "cpu_task_s_max": max(r[2] for r in res)}
+    for ev in ("fp64", "fp32"):
+        reqs = [request_from_dict(dict(w, eval=ev)) for w in sub]
+        zi.integrate_batch(reqs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        outs = zi.integrate_batch(reqs)
+        torch.cuda.synchronize()
+        row["gpu_%s_s" % ev] = time.perf_counter() - t0
+        row["gpu_%s_samples" % ev] = sum(o.n_samples for o in outs)
+        row["gpu_%s_max_rel_diff" % ev] = max(abs(o.integral - r[1]) / max(abs(r[1]), 1e-300)
+                                               for o, r in zip(outs, res))
+    row["speedup_gpu_fp32"] = cpu_s / row["gpu_fp32_s"]
+    out["genz_batch_every16th_n16_all_cores"] = row
+    print("batch subset: cpu %.1f s on %d cores, gpu fp32 %.4f s" % (cpu_s, P, row["gpu_fp32_s"]),
+          file=sys.stderr, flush=True)
     zi.close()
     return out
 
