@@ -95,9 +95,10 @@ def _bucket_rate(zi, name, D, ev, n_target, N, trials):
 
 
 def rate_table(evals=("fp32", "fp64"), dims=(2, 4, 6, 9, 12, 16), n_target=65536, N=16384, trials=3,
-               tune_path=None, names=None):
+               tune_path=None, names=None, roots=None):
     """Sampling-kernel rate per bucket from HIP-event kernel time, with the
-    fraction of the ALU roofline."""
+    fraction of the ALU roofline.  roots: several level sizes (minimum root
+    cubes) per bucket instead of n_target alone."""
     from paper_1902_07916_amd import Integrator
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import bench
@@ -108,13 +109,14 @@ def rate_table(evals=("fp32", "fp64"), dims=(2, 4, 6, 9, 12, 16), n_target=65536
             for D in dims:
                 if ev == "fp64" and D not in (4, 6, 9):
                     continue
-                cubes, sps = _bucket_rate(zi, name, D, ev, n_target, N, trials)
-                rl = bench.alu_roofline(sps, name, D, ev)
-                rows.append(dict(eval=ev, integrand=name, D=D, cubes=cubes, samples_per_s=sps, frac=rl["frac"],
-                                 int_issue_frac=rl["int_issue_frac"]))
-                print("%s %-11s D=%2d cubes=%7d %.3e samples/s  %5.1f%% of the VALU issue roofline, %5.1f%% of "
-                      "integer issue" % (ev, name, D, cubes, sps, 100 * rl["frac"], 100 * rl["int_issue_frac"]),
-                      flush=True)
+                for target in (roots or (n_target,)):
+                    cubes, sps = _bucket_rate(zi, name, D, ev, target, N, trials)
+                    rl = bench.alu_roofline(sps, name, D, ev)
+                    rows.append(dict(eval=ev, integrand=name, D=D, cubes=cubes, samples_per_s=sps, frac=rl["frac"],
+                                     int_issue_frac=rl["int_issue_frac"]))
+                    print("%s %-11s D=%2d cubes=%7d %.3e samples/s  %5.1f%% of the VALU issue roofline, %5.1f%% "
+                          "of integer issue" % (ev, name, D, cubes, sps, 100 * rl["frac"], 100 * rl["int_issue_frac"]),
+                          flush=True)
     zi.close()
     return rows
 
@@ -217,6 +219,8 @@ def main(argv=None) -> int:
     ap.add_argument("--waves", action="store_true",
                     help="time every occupancy variant of every registry bucket; write the fastest to --out")
     ap.add_argument("--tune-path", default=None, help="tuning file for --table")
+    ap.add_argument("--roots", default=None,
+                    help="with --table: comma-separated level sizes (minimum root cubes per level; default 65536)")
     ap.add_argument("--blocks", action="store_true",
                     help="time every block shape (64/128/256 threads) of every registry bucket; write the fastest "
                          "to --out")
@@ -224,7 +228,8 @@ def main(argv=None) -> int:
     if a.table:
         rate_table(evals=a.evals.split(","), N=a.samples, tune_path=a.tune_path,
                    dims=_parse_dims(a.dims) if a.dims else (2, 4, 6, 9, 12, 16),
-                   names=a.integrands.split(",") if a.integrands else None)
+                   names=a.integrands.split(",") if a.integrands else None,
+                   roots=[int(v) for v in a.roots.split(",")] if a.roots else None)
         return 0
     if a.blocks:
         if not a.out:
