@@ -76,18 +76,26 @@ def time_bucket(name: str, D: int, eval_: str, groups: int, n_cubes: int = 4096,
 REGISTRY = ("sin_sum", "gauss", "genz_osc", "genz_ppeak", "genz_cpeak", "genz_gauss")
 WAVE_HINTS = (1, 5, 7, 8)  # the library's occupancy variants (minimum waves per SIMD)
 MIN_GAIN = 1.015        # a variant must beat the unconstrained kernel by 1.5% to be chosen
+# Seconds of back-to-back runs of a bucket's level before it is timed: the
+# GPU clock rises over the first tens of milliseconds of load, and a short
+# level timed from a colder state runs up to 12% slower.
+WARM_S = 0.05
 
 
 def _bucket_rate(zi, name, D, ev, n_target, N, trials):
-    """Samples/s of the sampling launches (HIP events, best of 3) over one
-    level of d^D >= n_target root cubes of [0,1]^D."""
+    """Samples/s of the sampling launches (HIP events, best of 3, after
+    WARM_S of warm-up runs) over one level of d^D >= n_target root cubes of
+    [0,1]^D."""
     import torch
     from paper_1902_07916_amd import make_request
     d = 2
     while d ** D < n_target:
         d += 1
     req = make_request(name, _params(name, D), [0.0] * D, [1.0] * D, d, N, trials, 0, 1.0, 1, eval=ev)
+    t0 = time.perf_counter()
     zi.integrate_request(req)
+    while time.perf_counter() - t0 < WARM_S:
+        zi.integrate_request(req)
     torch.cuda.synchronize()
     rs = [zi.integrate_request(req) for _ in range(3)]
     ms = min(r.sample_ms_per_level[0] for r in rs)
